@@ -1,0 +1,239 @@
+"""Throughput of the Hermite-6 block-step path on one MI355X.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--precision fp64|split]
+
+Workload: a Plummer sphere of N = 65536 bodies (seed 2, equal masses, eps = 1e-4,
+Henon units), after the Hermite start-up on the GPU. A step is one whole block
+step over the full active set (all N bodies due): active-set selection, prediction
+of every body, pairwise evaluation of acceleration/jerk/snap/potential (N x N
+interactions), j-split reduction, corrector and new step levels. Before each step
+the post-start state is restored so every step does identical work; the timed
+region ends with one energy diagnostic (O(N^2), at the output time). Inputs are
+resident in HBM before timing starts.
+
+Prints one JSON line: value = interactions per second over the timed region
+(K * N^2 interactions / elapsed), the roofline of the evaluation kernel (stated 79
+flop per interaction against the FP64 vector peak), the nb_evaluate sweep over
+active-set sizes (median and p99 latency), and the CPU oracle timed on a bounded
+sample of the same evaluation.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+FLOP_PER_INTERACTION = 79          # stated count (see the design notes)
+PEAK_FP64_TFLOPS = 78.6            # 256 CU x 2.4 GHz x 128 FP64 flop/clk (vector)
+N_BODIES = 65536
+EPS = 1e-4
+DT_MAX, DT_MIN = -3, -40
+SWEEP = (1, 64, 1024, 8192, 65536)
+METRIC = "pairwise interactions/s (acc+jerk+snap) and % of FP64/FP32 vector peak; p99"
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--precision", choices=("fp64", "split"), default="fp64")
+    ap.add_argument("--n", type=int, default=N_BODIES)
+    ap.add_argument("--no-sweep", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--eval-only", type=int, default=0,
+                    help="time only K nb_evaluate calls of the full active set (for profiling)")
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+              "(the design notes describe how the evaluation would shard).", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import nbody_inputs as ni
+    import paper_1812_00367_amd as nb
+
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    n = args.n
+    prec = nb.NB_SPLIT if args.precision == "split" else nb.NB_FP64
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream(dev)
+
+    ic = ni.plummer(n, 2)
+    sim = nb.Simulation(n, eps=EPS, dt_max_log2=DT_MAX, dt_min_log2=DT_MIN, precision=prec,
+                        device=dev)
+    sim.set_state(ic.m, ic.x, ic.v)
+    sim.start()
+    st = sim.get_state()
+    L = DT_MAX - DT_MIN
+    kmax = int(st["level"].max().item())
+    # every body due at the same block time 2^(L - kmax): the smallest step any body needs
+    snap = {k: st[k].clone() for k in ("m", "x", "v", "a", "j", "s", "c", "a4n", "a5n")}
+    snap["tick"] = torch.zeros(n, dtype=torch.int64, device=dev)
+    snap["level"] = torch.full((n,), kmax, dtype=torch.int32, device=dev)
+    idx_buf = torch.empty(n, dtype=torch.int32, device=dev)
+    out_eval = None
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def restore():
+        sim.set_state(**snap)
+
+    def one_step(timed_eval=None):
+        idx, tn = sim.active(idx_buf)
+        sim.predict(tn)
+        if timed_eval is not None:
+            timed_eval[0].record(stream)
+        sim.evaluate_into(idx, out_buf)
+        if timed_eval is not None:
+            timed_eval[1].record(stream)
+        sim.correct(idx, tn)
+        sim.timesteps(idx)
+        return idx.shape[0]
+
+    out_buf = torch.empty((10, n), dtype=torch.float64, device=dev)
+
+    if args.eval_only:
+        restore()
+        idx, tn = sim.active(idx_buf)
+        sim.predict(tn)
+        for _ in range(args.warmup):
+            sim.evaluate_into(idx, out_buf)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.eval_only):
+            sim.evaluate_into(idx, out_buf)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / args.eval_only
+        print(json.dumps({"eval_only_ms": dt * 1e3, "interactions_per_s": n * n / dt}), flush=True)
+        return
+
+    for _ in range(args.warmup):
+        restore()
+        one_step()
+    torch.cuda.synchronize()
+    pairs = []
+    inter = 0
+    t_energy = 0.0
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        restore()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        na = one_step((e0, e1))
+        pairs.append((e0, e1))
+        inter += na * n
+    te = time.perf_counter()
+    ek, ep = sim.energy(1 << (L - kmax))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    t_energy = t1 - te
+    elapsed = t1 - t0
+    eval_ms = [a.elapsed_time(b) for a, b in pairs]
+    eval_avg_s = sum(eval_ms) / len(eval_ms) / 1e3
+    shape = sim.eval_config(None, n)
+    achieved = FLOP_PER_INTERACTION * n * n / eval_avg_s / 1e12
+    value = inter / elapsed
+
+    result = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "interactions/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if prec == nb.NB_FP64 else "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": "plummer-65536 full block step (Hermite-6, all bodies due)",
+                   "n": n, "n_act": n, "eps": EPS, "seed": 2, "precision": args.precision,
+                   "eta": 0.45, "level": kmax, "eval_shape": shape},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
+                     "kernel": "k_eval_f64" if prec == nb.NB_FP64 else "k_eval_split",
+                     "flop_per_interaction": FLOP_PER_INTERACTION,
+                     "eval_ms_avg": eval_avg_s * 1e3},
+        "energy": {"ekin": ek, "epot": ep, "ms": t_energy * 1e3},
+    }
+
+    if not args.no_sweep:
+        result["sweep"] = sweep(sim, ic, n, stream, dev)
+    if not args.no_cpu_baseline:
+        result["cpu_baseline"] = cpu_baseline(ic, n, args.cpu_seconds)
+    print(json.dumps(result), flush=True)
+
+
+def sweep(sim, ic, n, stream, dev):
+    """Single nb_evaluate calls over active-set sizes: median / p99 latency."""
+    import numpy as np
+    import torch
+
+    import nbody_inputs as ni
+    res = []
+    out = torch.empty((10, n), dtype=torch.float64, device=dev)
+    for k, na in enumerate(SWEEP):
+        if na > n:
+            continue
+        idx = torch.as_tensor(ni.active_subset(n, na, 20 + k), device=dev)
+        reps = 200 if na <= 1024 else 50
+        for _ in range(20):
+            sim.evaluate_into(idx, out)
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(reps)]
+        for a, b in ev:
+            a.record(stream)
+            sim.evaluate_into(idx, out)
+            b.record(stream)
+        torch.cuda.synchronize()
+        ms = np.array([a.elapsed_time(b) for a, b in ev])
+        med = float(np.median(ms))
+        res.append({"n_act": na, "median_ms": med, "p99_ms": float(np.percentile(ms, 99)),
+                    "interactions_per_s": na * n / (med / 1e3),
+                    "fp64_peak_frac": FLOP_PER_INTERACTION * na * n / (med / 1e3) / 1e12
+                    / PEAK_FP64_TFLOPS,
+                    "shape": sim.eval_config(None, na)})
+    return res
+
+
+def cpu_baseline(ic, n, seconds):
+    """The oracle's evaluation on a bounded sample of the active set."""
+    import numpy as np
+
+    import nbody_inputs as ni
+    import oracle
+    threads = oracle.default_threads()
+    ap = ni.plummer_mean_field_acc(ic.x)
+    probe = 64
+    t0 = time.perf_counter()
+    oracle.evaluate(ic.m, ic.x, ic.v, ap, EPS, idx=np.arange(probe, dtype=np.int32),
+                    nthreads=threads)
+    dt = time.perf_counter() - t0
+    k = int(min(n, max(probe, probe * seconds / max(dt, 1e-6))))
+    k = max(threads, k // threads * threads)
+    idx = ni.active_subset(n, k, 99)
+    t0 = time.perf_counter()
+    oracle.evaluate(ic.m, ic.x, ic.v, ap, EPS, idx=idx, nthreads=threads)
+    dt = time.perf_counter() - t0
+    return {"value": k * n / dt, "unit": "interactions/s", "cores": threads, "kind": "oracle",
+            "sample": f"{k} active bodies x {n} bodies (plummer-65536), "
+                      f"{k * n:.3e} interactions in {dt:.1f} s"}
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,197 @@
+/*
+ * nbody.h -- C ABI of the MI355X (gfx950) Hermite 6th-order block-step N-body
+ * library (libnbody.so).
+ *
+ * The method is the direct N-body scheme of Goz et al., "Astrophysical code
+ * migration into Exascale Era" (section "Code implementation": Hermite 6th-order
+ * integrator, double precision for inter-particle distances and accelerations,
+ * an extended-precision float-float alternative; section "Performance results":
+ * the O(N^2) evaluation as the dominant kernel). The paper prints no formula; the
+ * formulas used are the standard 6th-order Hermite scheme (Nitadori & Makino 2008)
+ * with power-of-two block steps (Makino 1991; Aarseth 2003). Each call below names
+ * the step of the block-step cycle it performs:
+ *
+ *     nb_active    -> next block time and the bodies due at it
+ *     nb_predict   -> Taylor prediction of every body to that time
+ *     nb_evaluate  -> acceleration, jerk, snap, potential of the due bodies (O(N_act N))
+ *     nb_correct   -> 6th-order Hermite corrector of the due bodies
+ *     nb_timesteps -> new power-of-two steps of the due bodies
+ *     nb_energy    -> total energy (diagnostic, O(N^2))
+ *
+ * Conventions
+ *   - Device pointers ("d_") are HIP device addresses on the context's device;
+ *     host pointers ("h_") are ordinary host memory.
+ *   - Vectors are structure-of-arrays, component-major: x[k*n + i], k = 0, 1, 2.
+ *   - Time is an int64 tick count; one tick is 2^dt_min_log2 time units. A body on
+ *     level k has step 2^(dt_max_log2 - k). Units: G = 1.
+ *   - Evaluation results are out[c*n_act + q], c = 0..9 = ax ay az jx jy jz sx sy sz
+ *     phi, for the q-th entry of the index list.
+ *   - Index lists are int32, strictly ascending, each in [0, n).
+ *
+ * Ownership: the caller owns all device memory. nb_create carves every device
+ * array the library uses out of one caller-provided workspace, which must stay
+ * valid until nb_destroy. The library owns only the host-side context (and a few
+ * bytes of pinned host memory for results). It never allocates device memory.
+ *
+ * Ordering: every call is enqueued on the stream given in nb_params and returns
+ * without waiting, except nb_active, nb_step, nb_energy and nb_get_state, which
+ * wait for the stream (they return values to the host). Input arrays passed to an
+ * asynchronous call must stay valid until the stream reaches it.
+ *
+ * Errors: no C++ exception crosses this boundary; every call returns an
+ * nb_status and nb_last_error() gives a message. Argument errors found on the
+ * host are returned at once. Errors found by kernels (an index out of range, a
+ * non-finite corrector result, a step below dt_min) are latched in a device word
+ * and returned by the next waiting call, which then clears the word.
+ * One host thread at a time may use a context.
+ */
+#ifndef NBODY_H
+#define NBODY_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct nb_ctx nb_ctx; /* opaque, library-owned host object */
+
+typedef enum {
+    NB_OK = 0,
+    NB_ERR_ARG = 1,     /* a bad argument (host check) or a bad index (device check) */
+    NB_ERR_SPACE = 2,   /* workspace smaller than nb_workspace_bytes() */
+    NB_ERR_DEVICE = 3,  /* a HIP runtime error */
+    NB_ERR_STATE = 4,   /* calls out of order (e.g. nb_correct without nb_evaluate) */
+    NB_ERR_NUMERIC = 5  /* non-finite values, or a body needs a step below dt_min */
+} nb_status;
+
+typedef enum {
+    NB_FP64 = 0,  /* everything in IEEE binary64 */
+    NB_SPLIT = 1  /* evaluation: float-float differences, FP32 algebra, FP64 sums */
+} nb_precision;
+
+typedef struct {
+    int64_t n;            /* number of bodies, 1 <= n <= 2^30 */
+    double eps;           /* Plummer softening length, >= 0 */
+    double eta;           /* accuracy parameter of the 6th-order step criterion (> 0) */
+    double eta_init;      /* accuracy parameter of the initial-step rule (> 0) */
+    int32_t dt_max_log2;  /* largest step 2^dt_max_log2 */
+    int32_t dt_min_log2;  /* tick size and smallest step 2^dt_min_log2;
+                             0 <= dt_max_log2 - dt_min_log2 <= 62 */
+    int32_t precision;    /* nb_precision of nb_evaluate */
+    int32_t reserved;     /* must be 0 */
+    int64_t partial_slots;/* capacity of the j-split partial-sum buffer in
+                             (split x active body) units; 0 = default max(4n, 2^20) */
+    void *stream;         /* hipStream_t for every launch; NULL = the null stream */
+} nb_params;
+
+/* A view of the full body state, for nb_set_state (read) and nb_get_state
+ * (written). Every pointer is a device address; NULL fields are skipped.
+ * Shapes: m, a4n, a5n, phi, tick, level: [n]; x, v, a, j, s, c: [3][n]. */
+typedef struct {
+    double *m;      /* masses */
+    double *x, *v;  /* position, velocity at the body's own time */
+    double *a, *j, *s; /* acceleration, jerk, snap at the body's own time */
+    double *c;      /* third derivative of a (interpolated by the corrector) */
+    double *a4n, *a5n; /* |4th| and |5th| derivative of a (from the corrector) */
+    double *phi;    /* potential from the body's last evaluation (read-only) */
+    int64_t *tick;  /* the body's own time, in ticks */
+    int32_t *level; /* the body's step level */
+} nb_state;
+
+/* Size in bytes of the device workspace a context with these parameters needs.
+ * Returns NB_ERR_ARG for invalid parameters. Touches no device. */
+nb_status nb_workspace_bytes(const nb_params *p, size_t *h_bytes);
+
+/* Create a context over d_workspace (device memory of at least
+ * nb_workspace_bytes() bytes, 256-byte aligned, owned by the caller). The state is
+ * zero until nb_set_state. Returns NB_ERR_SPACE if the workspace is too small. */
+nb_status nb_create(const nb_params *p, void *d_workspace, size_t bytes, nb_ctx **out);
+
+/* Destroy a context (NULL is accepted). Waits for its stream. Does not free the
+ * workspace. */
+void nb_destroy(nb_ctx *ctx);
+
+/* Message of the last error on this context ("" if none). Valid until the next call. */
+const char *nb_last_error(const nb_ctx *ctx);
+
+/* Load a state. m, x and v are required. a, j, s, c, a4n, a5n default to 0, tick to
+ * tick0 for every body and level to 0 when NULL. If tick is NULL the state is
+ * "synchronised at tick0" and nb_start may be called; a full state (tick and
+ * level given) resumes a run exactly (checkpoint restore). Asynchronous. */
+nb_status nb_set_state(nb_ctx *ctx, const nb_state *src, int64_t tick0);
+
+/* Copy the state into the non-NULL fields of dst (device arrays). Waits. */
+nb_status nb_get_state(nb_ctx *ctx, const nb_state *dst);
+
+/* Hermite start-up on a synchronised state: two evaluations of every body (the
+ * first gives a and j, the second s with the predicted accelerations set to the
+ * first a), c = 0, then the initial-step rule for every body. Asynchronous. */
+nb_status nb_start(nb_ctx *ctx);
+
+/* Block-step selection: tick_next = min over bodies of (tick + step) and the
+ * ascending list of bodies with tick + step == tick_next, written to d_idx_out
+ * (capacity n). Returns the count in *h_n_act and the time in *h_tick_next. Waits. */
+nb_status nb_active(nb_ctx *ctx, int32_t *d_idx_out, int64_t *h_n_act,
+                    int64_t *h_tick_next);
+
+/* Predict every body to tick (>= every body's own time) with its Taylor series
+ * up to the third derivative of a; the result feeds nb_evaluate. Asynchronous. */
+nb_status nb_predict(nb_ctx *ctx, int64_t tick);
+
+/* Copy the predicted positions, velocities and accelerations of the last
+ * nb_predict into [3][n] device arrays (NULL skipped). Asynchronous. */
+nb_status nb_get_predicted(nb_ctx *ctx, double *d_xp, double *d_vp, double *d_ap);
+
+/* Acceleration, jerk, snap and potential of the n_act bodies d_idx against all
+ * n predicted bodies (self pair excluded), in the precision chosen at
+ * nb_create. The result is kept for nb_correct and, if d_out is not NULL, also
+ * written to d_out[10][n_act]. n_act = 0 is a no-op. Asynchronous. */
+nb_status nb_evaluate(nb_ctx *ctx, const int32_t *d_idx, int64_t n_act, double *d_out);
+
+/* Supply the evaluation of the bodies d_idx from outside instead of nb_evaluate:
+ * d_in[10][n_act] (same layout as nb_evaluate's output) becomes the result that
+ * the next nb_correct with the same d_idx and n_act uses. This is how partial sums
+ * computed elsewhere (another device's share of the j-bodies, after a sum over
+ * devices) enter the corrector. Asynchronous. */
+nb_status nb_set_evaluation(nb_ctx *ctx, const int32_t *d_idx, int64_t n_act,
+                            const double *d_in);
+
+/* Launch shape of nb_evaluate, for tuning and tests: h_cfg = {bodies per lane
+ * (1 or 2), waves per workgroup (1 or 4), LDS tile (64 or 256 bodies), j-splits S
+ * (>= 1)}; supported combinations are {2,4,256}, {1,4,256} and {1,1,64}. All zeros
+ * (or h_cfg NULL) restores the built-in choice. The shape never changes results
+ * beyond FP64 rounding of the split sums. Host-only; returns NB_ERR_ARG for an
+ * unsupported combination. h_shape_out (may be NULL) receives the shape the next
+ * call with n_act bodies will use: {ipl, waves, tile, jchunk, splits, iblocks}. */
+nb_status nb_eval_config(nb_ctx *ctx, const int32_t *h_cfg, int64_t n_act,
+                         int32_t *h_shape_out);
+
+/* Hermite 6th-order corrector of the bodies of the last nb_evaluate (same d_idx,
+ * n_act) to tick, using that evaluation. Updates x, v, a, j, s, c, a4n, a5n and
+ * sets their time to tick. Asynchronous. */
+nb_status nb_correct(nb_ctx *ctx, const int32_t *d_idx, int64_t n_act, int64_t tick);
+
+/* New step levels of the bodies d_idx at their current time: the 6th-order
+ * criterion and the block rules (init = 0), or the initial-step rule (init = 1).
+ * Asynchronous; a body needing a step below dt_min is reported by the next
+ * waiting call as NB_ERR_NUMERIC. */
+nb_status nb_timesteps(nb_ctx *ctx, const int32_t *d_idx, int64_t n_act, int init);
+
+/* One whole block step: nb_active, nb_predict, nb_evaluate, nb_correct and
+ * nb_timesteps in order, with the active list kept in the workspace. Returns the
+ * step's time and size. If tick_limit >= 0 and the next block time is beyond it,
+ * nothing is done and *h_n_act is 0. Waits (after selecting the active set). */
+nb_status nb_step(nb_ctx *ctx, int64_t tick_limit, int64_t *h_n_act, int64_t *h_tick_next);
+
+/* Total energy at tick: every body is predicted to tick (this overwrites the
+ * predicted state), then E_kin = sum m v^2 / 2 and
+ * E_pot = -1/2 sum_i sum_{j != i} m_i m_j / sqrt(r^2 + eps^2). Waits. */
+nb_status nb_energy(nb_ctx *ctx, int64_t tick, double *h_ekin, double *h_epot);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NBODY_H */

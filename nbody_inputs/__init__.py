@@ -26,6 +26,8 @@ __all__ = [
     "parabolic_pair",
     "log_uniform_n",
     "active_subset",
+    "plummer_mean_field_acc",
+    "block_state",
 ]
 
 # Mass fraction at which the Plummer radius draw is truncated (the tail beyond it
@@ -191,3 +193,23 @@ def active_subset(n: int, n_act: int, seed: int) -> np.ndarray:
         return np.arange(n, dtype=np.int32)
     g = rng(seed)
     return np.sort(g.choice(n, size=n_act, replace=False)).astype(np.int32)
+
+
+def plummer_mean_field_acc(x: np.ndarray, mass: float = 1.0) -> np.ndarray:
+    """Acceleration of the smooth Plummer potential at positions x[3][n], in the
+    Henon-unit scaling used by ``plummer`` (scale radius 3 pi / 16):
+    a = -M x / (|x|^2 + b^2)^(3/2). A closed-form stand-in, with the right
+    magnitudes and directions, for the predicted accelerations of a Plummer sphere."""
+    b = 3.0 * math.pi / 16.0
+    r2 = (x * x).sum(axis=0) + b * b
+    return -mass * x / r2 ** 1.5
+
+
+def block_state(n: int, seed: int, L: int, max_level: int = 10, span: int = 64):
+    """A random, valid block-time-step bookkeeping state: levels in [0, max_level]
+    and each body's tick a multiple of its own step 2^(L - level)."""
+    g = rng(seed)
+    level = g.integers(0, max_level + 1, n).astype(np.int32)
+    mult = g.integers(0, span, n).astype(np.int64)
+    tick = mult * (np.int64(1) << (L - level.astype(np.int64)))
+    return tick, level

@@ -1,0 +1,93 @@
+// nb_internal.h -- private interface between the host ABI (nbody_abi.hip) and the
+// gfx950 kernels (nbody_kernels.hip). Not installed; not part of the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace nb {
+
+// Predicted j-stream record of the FP64 path: 10 doubles = 80 bytes per body,
+// {x, y, z, vx, vy, vz, ax, ay, az, m}, so that one tile of bodies is one
+// contiguous block and a record is five 16-byte loads.
+constexpr int kRecD = 10;
+// Split-precision record: 16 floats = 64 bytes per body,
+// {xh, yh, zh, m, xl, yl, zl, 0, vx, vy, vz, 0, ax, ay, az, 0}
+// (x = xh + xl exactly to about 48 bits; v, a, m rounded to FP32).
+constexpr int kRecF = 16;
+
+// Device error words (one word per kind; kernels store 1, the host clears).
+enum ErrWord : int { kErrIndex = 0, kErrNumeric = 1, kErrDtMin = 2, kErrLevel = 3, kErrWords = 4 };
+
+// Small device block read back by the waiting calls.
+struct Status {
+    int64_t tick_next;
+    int64_t n_act;
+    double ekin;
+    double epot;
+    int32_t err[kErrWords];
+    int64_t pad[2];
+};
+
+// Device arrays carved from the workspace.
+struct Arrays {
+    double *m, *x, *v, *a, *j, *s, *c, *a4n, *a5n, *phi;
+    int64_t *tick;
+    int32_t *level;
+    double *jrec;      // [n][kRecD]
+    float *jrec32;     // [n][kRecF] or nullptr
+    double *evalbuf;   // [10][n]
+    double *part;      // [10 * partial_slots]
+    int32_t *act_idx;  // [n]
+    int64_t *act_bmin; // [act_blocks]
+    int32_t *act_bcnt; // [act_blocks]
+    double *en_bsum;   // [2][en_blocks]
+    Status *status;
+};
+
+// Launch shape of one evaluation.
+struct EvalPlan {
+    int ipl;     // active bodies per lane
+    int waves;   // waves per workgroup
+    int tile;    // j-records per LDS tile
+    int jchunk;  // j-records per split (multiple of tile)
+    int splits;  // number of j-splits S
+    int iblocks; // workgroups along the active bodies
+};
+
+constexpr int kActBS = 256;
+constexpr int kActPerThread = 8;
+constexpr int kActChunk = kActBS * kActPerThread;
+constexpr int kEnBS = 256;
+
+// ---- launchers (all asynchronous on `st`) ----
+hipError_t launch_fill_f64(double *p, double v, size_t count, hipStream_t st);
+hipError_t launch_fill_i64(int64_t *p, int64_t v, size_t count, hipStream_t st);
+hipError_t launch_fill_i32(int32_t *p, int32_t v, size_t count, hipStream_t st);
+hipError_t launch_iota(int32_t *p, int64_t count, hipStream_t st);
+
+hipError_t launch_predict(const Arrays &A, int64_t n, int64_t tick, int dt_min_log2,
+                          bool split, hipStream_t st);
+hipError_t launch_get_predicted(const Arrays &A, int64_t n, double *xp, double *vp, double *ap,
+                                hipStream_t st);
+hipError_t launch_copy_acc_to_jrec(const Arrays &A, int64_t n, bool split, hipStream_t st);
+hipError_t launch_start_store(const Arrays &A, int64_t n, hipStream_t st);
+
+EvalPlan plan_eval(int64_t n, int64_t n_act, int64_t partial_slots, bool split);
+hipError_t launch_eval(const Arrays &A, const EvalPlan &P, int64_t n, const int32_t *idx,
+                       int64_t n_act, double eps, bool split, double *out, hipStream_t st);
+
+hipError_t launch_correct(const Arrays &A, int64_t n, const int32_t *idx, int64_t n_act,
+                          int64_t tick, int dt_min_log2, hipStream_t st);
+hipError_t launch_timesteps(const Arrays &A, int64_t n, const int32_t *idx, int64_t n_act,
+                            int init, double eta, double eta_init, int dt_max_log2,
+                            int dt_min_log2, hipStream_t st);
+hipError_t launch_active(const Arrays &A, int64_t n, int L, int32_t *idx_out, hipStream_t st);
+hipError_t launch_energy(const Arrays &A, int64_t n, double eps, int64_t partial_slots,
+                         hipStream_t st);
+
+int act_blocks(int64_t n);
+int en_blocks(int64_t n);
+
+}  // namespace nb
