@@ -122,6 +122,12 @@ const char *nb_last_error(const nb_ctx *ctx);
  * level given) resumes a run exactly (checkpoint restore). Asynchronous. */
 nb_status nb_set_state(nb_ctx *ctx, const nb_state *src, int64_t tick0);
 
+/* Load only the time bookkeeping: every body's own time d_tick[n] (ticks) and step
+ * level d_level[n] (device arrays); positions, velocities and derivatives are
+ * kept. Used to re-arm a block schedule (for instance to make every body due at
+ * the same time) without reloading the physical state. Asynchronous. */
+nb_status nb_set_times(nb_ctx *ctx, const int64_t *d_tick, const int32_t *d_level);
+
 /* Copy the state into the non-NULL fields of dst (device arrays). Waits. */
 nb_status nb_get_state(nb_ctx *ctx, const nb_state *dst);
 

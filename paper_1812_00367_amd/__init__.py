@@ -141,6 +141,14 @@ class Simulation:
         # next call is enough because torch reuses freed memory in stream order
         self._keepalive = keep
 
+    def set_times(self, tick, level):
+        """Reload every body's time (ticks) and step level; the physical state is kept."""
+        torch = _torch()
+        tick = self._dev(tick, torch.int64, (self.n,))
+        level = self._dev(level, torch.int32, (self.n,))
+        self._check(self._lib.nb_set_times(self._ctx, _ptr(tick), _ptr(level)))
+        self._times_keep = (tick, level)
+
     def get_state(self):
         torch = _torch()
         n = self.n

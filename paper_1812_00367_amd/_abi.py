@@ -17,7 +17,7 @@ STATUS_NAMES = {0: "NB_OK", 1: "NB_ERR_ARG", 2: "NB_ERR_SPACE", 3: "NB_ERR_DEVIC
 
 # Every function the header declares (checked against include/nbody.h by the tests).
 EXPORTS = ["nb_workspace_bytes", "nb_create", "nb_destroy", "nb_last_error", "nb_set_state",
-           "nb_get_state", "nb_start", "nb_active", "nb_predict", "nb_get_predicted",
+           "nb_set_times", "nb_get_state", "nb_start", "nb_active", "nb_predict", "nb_get_predicted",
            "nb_evaluate", "nb_set_evaluation", "nb_eval_config", "nb_correct", "nb_timesteps",
            "nb_step", "nb_energy"]
 
@@ -69,6 +69,7 @@ def load(path: str = LIB_PATH):
     lib.nb_last_error.argtypes = [vp]
     lib.nb_last_error.restype = ctypes.c_char_p
     lib.nb_set_state.argtypes = [vp, P(State), i64]
+    lib.nb_set_times.argtypes = [vp, vp, vp]
     lib.nb_get_state.argtypes = [vp, P(State)]
     lib.nb_start.argtypes = [vp]
     lib.nb_active.argtypes = [vp, vp, P(i64), P(i64)]

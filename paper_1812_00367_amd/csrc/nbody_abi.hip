@@ -305,6 +305,22 @@ nb_status nb_set_state(nb_ctx *c, const nb_state *src, int64_t tick0)
     return NB_OK;
 }
 
+nb_status nb_set_times(nb_ctx *c, const int64_t *d_tick, const int32_t *d_level)
+{
+    NB_CTX(c);
+    if (!d_tick || !d_level)
+        return fail(c, NB_ERR_ARG, "tick and level are required");
+    if (!c->have_state)
+        return fail(c, NB_ERR_STATE, "no state loaded");
+    const size_t n = (size_t)c->p.n;
+    NB_HIP(c, hipMemcpyAsync(c->A.tick, d_tick, 8 * n, hipMemcpyDeviceToDevice, c->st));
+    NB_HIP(c, hipMemcpyAsync(c->A.level, d_level, 4 * n, hipMemcpyDeviceToDevice, c->st));
+    c->synced = false;
+    c->predicted = false;
+    c->eval_valid = false;
+    return NB_OK;
+}
+
 nb_status nb_get_state(nb_ctx *c, const nb_state *dst)
 {
     NB_CTX(c);

@@ -91,12 +91,16 @@ __device__ __forceinline__ int wave_sum_i32(int v)
     return v;
 }
 
-// 1/sqrt(x) to about one ulp: the hardware estimate (relative error below 2^-22)
-// followed by one third-order correction y (1 + e/2 + 3 e^2 / 8), e = 1 - x y^2,
-// whose truncation error (5/16) e^3 is far below the FP64 rounding.
+// 1/sqrt(x) to about one ulp for 2^-126 <= x < 2^128: an FP32 hardware estimate
+// (v_rsq_f32, relative error below 2^-23 measured; it issues in about 2 FP64-FMA
+// slots against 4 for v_rsq_f64, whose estimate is no more accurate), then one
+// third-order correction y (1 + e/2 + 3 e^2 / 8) with e = 1 - x y^2, whose
+// truncation error (5/16) e^3 ~ 2^-67 is far below the FP64 rounding.
+// Callers keep x inside that range: softened squared distances, the masked self
+// pair (1) and the padding records (about 3e36).
 __device__ __forceinline__ double rsqrt_f64(double x)
 {
-    const double y = __builtin_amdgcn_rsq(x);
+    const double y = (double)__builtin_amdgcn_rsqf((float)x);
     const double e = __builtin_fma(-x, y * y, 1.0);
     const double p = __builtin_fma(e, 0.375, 0.5);
     return __builtin_fma(y, e * p, y);
@@ -311,29 +315,33 @@ __global__ __launch_bounds__(64 * NW) void k_eval_f64(Arrays A, int n, const int
     lo = wave_min_i32(lo);
     hi = wave_max_i32(hi);
 
+    // Tile staging: every thread issues its CPT 16-byte loads unconditionally (an
+    // out-of-range chunk reloads chunk 0) so they stay in flight during the
+    // previous tile's arithmetic; padding is substituted when storing to LDS.
     const double2 *__restrict__ src = reinterpret_cast<const double2 *>(jrec);
     const int ntiles = (jend - jbeg + TILE - 1) / TILE;
     double2 stage[CPT];
+    int valid = 0;
     auto gload = [&](int t) {
         const int j0 = jbeg + t * TILE;
-        const int valid = (jend - j0) * 5;
+        valid = (jend - j0) * 5;
 #pragma unroll
         for (int c = 0; c < CPT; ++c) {
             const int ch = c * BS + tid;
-            if (ch < valid) {
-                stage[c] = src[(size_t)j0 * 5 + ch];
-            } else {
-                const int part5 = ch % 5;
-                stage[c] = part5 == 0 ? make_double2(kFar, kFar)
-                         : part5 == 1 ? make_double2(kFar, 0.0)
-                                      : make_double2(0.0, 0.0);
-            }
+            stage[c] = src[ch < valid ? (size_t)j0 * 5 + ch : 0];
         }
     };
     auto lstore = [&](int buf) {
 #pragma unroll
-        for (int c = 0; c < CPT; ++c)
-            lds[buf][c * BS + tid] = stage[c];
+        for (int c = 0; c < CPT; ++c) {
+            const int ch = c * BS + tid;
+            const bool ok = ch < valid;
+            const int part5 = ch % 5;  // padding record {far, far, far, 0 ... 0, m = 0}
+            double2 v;
+            v.x = ok ? stage[c].x : (part5 <= 1 ? kFar : 0.0);
+            v.y = ok ? stage[c].y : (part5 == 0 ? kFar : 0.0);
+            lds[buf][ch] = v;
+        }
     };
 
     if (ntiles > 0) {
@@ -348,13 +356,17 @@ __global__ __launch_bounds__(64 * NW) void k_eval_f64(Arrays A, int n, const int
         const int j0 = jbeg + t * TILE;
         const double2 *L = lds[buf];
         if (hi < j0 || lo >= j0 + TILE) {
+            // the next record's LDS reads are issued before this record's arithmetic
+            double2 p0 = L[0], p1 = L[1], p2 = L[2], p3 = L[3], p4 = L[4];
 #pragma unroll 2
             for (int jj = 0; jj < TILE; ++jj) {
-                const double2 p0 = L[jj * 5 + 0], p1 = L[jj * 5 + 1], p2 = L[jj * 5 + 2],
-                              p3 = L[jj * 5 + 3], p4 = L[jj * 5 + 4];
+                const int nx = (jj + 1 < TILE ? jj + 1 : jj) * 5;
+                const double2 n0 = L[nx + 0], n1 = L[nx + 1], n2 = L[nx + 2], n3 = L[nx + 3],
+                              n4 = L[nx + 4];
 #pragma unroll
                 for (int q = 0; q < IPL; ++q)
                     interact_f64<false>(b[q], p0, p1, p2, p3, p4, eps2, 0);
+                p0 = n0; p1 = n1; p2 = n2; p3 = n3; p4 = n4;
             }
         } else {
             for (int jj = 0; jj < TILE; ++jj) {
@@ -496,23 +508,29 @@ __global__ __launch_bounds__(64 * NW) void k_eval_split(Arrays A, int n, const i
     const float4 *__restrict__ src = reinterpret_cast<const float4 *>(jrec);
     const int ntiles = (jend - jbeg + TILE - 1) / TILE;
     float4 stage[CPT];
+    int valid = 0;
     auto gload = [&](int t) {
         const int j0 = jbeg + t * TILE;
-        const int valid = (jend - j0) * 4;
+        valid = (jend - j0) * 4;
 #pragma unroll
         for (int c = 0; c < CPT; ++c) {
             const int ch = c * BS + tid;
-            if (ch < valid)
-                stage[c] = src[(size_t)j0 * 4 + ch];
-            else
-                stage[c] = (ch % 4) == 0 ? make_float4(1.0e18f, 1.0e18f, 1.0e18f, 0.0f)
-                                         : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            stage[c] = src[ch < valid ? (size_t)j0 * 4 + ch : 0];
         }
     };
     auto lstore = [&](int buf) {
 #pragma unroll
-        for (int c = 0; c < CPT; ++c)
-            lds[buf][c * BS + tid] = stage[c];
+        for (int c = 0; c < CPT; ++c) {
+            const int ch = c * BS + tid;
+            const bool ok = ch < valid;
+            const bool first = (ch % 4) == 0;  // padding record {far, far, far, m = 0, 0 ...}
+            float4 v;
+            v.x = ok ? stage[c].x : (first ? 1.0e18f : 0.0f);
+            v.y = ok ? stage[c].y : (first ? 1.0e18f : 0.0f);
+            v.z = ok ? stage[c].z : (first ? 1.0e18f : 0.0f);
+            v.w = ok ? stage[c].w : 0.0f;
+            lds[buf][ch] = v;
+        }
     };
     auto fold = [&]() {
 #pragma unroll
@@ -573,20 +591,48 @@ __global__ __launch_bounds__(64 * NW) void k_eval_split(Arrays A, int n, const i
     }
 }
 
-// Fixed-order sum over the S j-splits: out[e] = sum_{s=0}^{S-1} part[s][e].
+// Sum over the S j-splits, out[e] = sum_s part[s][e], in a fixed order: G threads
+// share an element, thread g adds s = g, g + G, ... in turn (four independent
+// chains, combined in a fixed pattern), then the G results are combined by a fixed
+// tree in LDS. G grows with S so that a large S is not one long chain of
+// dependent loads; for a given (S, count) the order is always the same.
+template <int G>
 __global__ __launch_bounds__(256) void k_reduce_splits(const double *__restrict__ part, int S,
                                                        int64_t count, double *__restrict__ dst,
                                                        double *__restrict__ dst2)
 {
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= count)
-        return;
-    double acc = part[e];
-    for (int s = 1; s < S; ++s)
-        acc += part[(size_t)s * count + e];
-    dst[e] = acc;
-    if (dst2)
-        dst2[e] = acc;
+    constexpr int E = 256 / G;  // elements per workgroup
+    __shared__ double red[256];
+    const int el = threadIdx.x % E, g = threadIdx.x / E;
+    const int64_t e = (int64_t)blockIdx.x * E + el;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    if (e < count) {
+        int s = g;
+        for (; s + 3 * G < S; s += 4 * G) {
+            a0 += part[(size_t)s * count + e];
+            a1 += part[(size_t)(s + G) * count + e];
+            a2 += part[(size_t)(s + 2 * G) * count + e];
+            a3 += part[(size_t)(s + 3 * G) * count + e];
+        }
+        for (; s < S; s += G)
+            a0 += part[(size_t)s * count + e];
+    }
+    double acc = (a0 + a1) + (a2 + a3);
+    if (G > 1) {
+        red[threadIdx.x] = acc;
+        __syncthreads();
+        for (int w = G / 2; w > 0; w >>= 1) {
+            if (g < w)
+                red[threadIdx.x] += red[threadIdx.x + w * E];
+            __syncthreads();
+        }
+        acc = red[threadIdx.x];
+    }
+    if (g == 0 && e < count) {
+        dst[e] = acc;
+        if (dst2)
+            dst2[e] = acc;
+    }
 }
 
 // ---------------------------------------------------------------- corrector ----
@@ -1088,8 +1134,16 @@ hipError_t launch_eval(const Arrays &A, const EvalPlan &P, int64_t n, const int3
         return e;
     const int64_t count = 10 * n_act;
     if (P.splits > 1) {
-        hipLaunchKernelGGL(k_reduce_splits, dim3(blocks_for(count, 256)), dim3(256), 0, st,
-                           (const double *)A.part, P.splits, count, A.evalbuf, out);
+        const double *pp = A.part;
+        if (P.splits <= 16)
+            hipLaunchKernelGGL(k_reduce_splits<1>, dim3(blocks_for(count, 256)), dim3(256), 0, st,
+                               pp, P.splits, count, A.evalbuf, out);
+        else if (P.splits <= 128)
+            hipLaunchKernelGGL(k_reduce_splits<8>, dim3(blocks_for(count, 32)), dim3(256), 0, st,
+                               pp, P.splits, count, A.evalbuf, out);
+        else
+            hipLaunchKernelGGL(k_reduce_splits<64>, dim3(blocks_for(count, 4)), dim3(256), 0, st,
+                               pp, P.splits, count, A.evalbuf, out);
         return hipGetLastError();
     }
     if (out)
