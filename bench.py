@@ -24,6 +24,7 @@ sample of the same evaluation.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -39,6 +40,11 @@ EPS = 1e-4
 DT_MAX, DT_MIN = -3, -40
 SWEEP = (1, 64, 1024, 8192, 65536)
 METRIC = "pairwise interactions/s (acc+jerk+snap) and % of FP64/FP32 vector peak; p99"
+PEAK_FP32_TFLOPS = 157.3           # packed FP32; unpacked FP32 issues at the FP64 rate
+KERNEL_SRC = os.path.join(ROOT, "paper_1812_00367_amd", "csrc", "nbody_kernels.hip")
+# HBM bytes per full-N FP64 evaluation launch from the FETCH_SIZE / WRITE_SIZE runs in
+# profiles/eval_fp64_plummer65536.md, valid only for the kernel source they were taken on.
+TRAFFIC = {"949a00bf00eba2e5": {"fp64": 2.00 * 21970 * 1024 + 81920 * 1024}}
 
 
 def parse():
@@ -53,6 +59,9 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--eval-only", type=int, default=0,
                     help="time only K nb_evaluate calls of the full active set (for profiling)")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="also run one device-to-device copy of this many MiB (a known-size "
+                         "kernel against which HBM byte counters are scaled)")
     return ap.parse_args()
 
 
@@ -110,6 +119,14 @@ def main():
 
     out_buf = torch.empty((10, n), dtype=torch.float64, device=dev)
 
+    if args.calib_copy_mib:
+        a = torch.ones(args.calib_copy_mib * (1 << 20) // 8, dtype=torch.float64, device=dev)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+
     if args.eval_only:
         restore()
         idx, tn = sim.active(idx_buf)
@@ -149,7 +166,11 @@ def main():
     eval_avg_s = sum(eval_ms) / len(eval_ms) / 1e3
     shape = sim.eval_config(None, n)
     achieved = FLOP_PER_INTERACTION * n * n / eval_avg_s / 1e12
+    peak = PEAK_FP64_TFLOPS if prec == nb.NB_FP64 else PEAK_FP32_TFLOPS
     value = inter / elapsed
+    with open(KERNEL_SRC, "rb") as f:
+        src_hash = hashlib.sha256(f.read()).hexdigest()[:16]
+    traffic = TRAFFIC.get(src_hash, {}).get(args.precision) if n == N_BODIES else None
 
     result = {
         "metric": METRIC,
@@ -167,22 +188,23 @@ def main():
         "config": {"workload": "plummer-65536 full block step (Hermite-6, all bodies due)",
                    "n": n, "n_act": n, "eps": EPS, "seed": 2, "precision": args.precision,
                    "eta": 0.45, "level": kmax, "eval_shape": shape},
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": peak,
+                     "unit": "TFLOP/s", "frac": achieved / peak, "traffic": traffic,
                      "kernel": "k_eval_f64" if prec == nb.NB_FP64 else "k_eval_split",
                      "flop_per_interaction": FLOP_PER_INTERACTION,
-                     "eval_ms_avg": eval_avg_s * 1e3},
+                     "algorithmic_bytes": 80 * n + 152 * n,
+                     "eval_ms_avg": eval_avg_s * 1e3, "kernel_src": src_hash},
         "energy": {"ekin": ek, "epot": ep, "ms": t_energy * 1e3},
     }
 
     if not args.no_sweep:
-        result["sweep"] = sweep(sim, ic, n, stream, dev)
+        result["sweep"] = sweep(sim, ic, n, stream, dev, peak)
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(ic, n, args.cpu_seconds)
     print(json.dumps(result), flush=True)
 
 
-def sweep(sim, ic, n, stream, dev):
+def sweep(sim, ic, n, stream, dev, peak):
     """Single nb_evaluate calls over active-set sizes: median / p99 latency."""
     import numpy as np
     import torch
@@ -208,8 +230,7 @@ def sweep(sim, ic, n, stream, dev):
         med = float(np.median(ms))
         res.append({"n_act": na, "median_ms": med, "p99_ms": float(np.percentile(ms, 99)),
                     "interactions_per_s": na * n / (med / 1e3),
-                    "fp64_peak_frac": FLOP_PER_INTERACTION * na * n / (med / 1e3) / 1e12
-                    / PEAK_FP64_TFLOPS,
+                    "peak_frac": FLOP_PER_INTERACTION * na * n / (med / 1e3) / 1e12 / peak,
                     "shape": sim.eval_config(None, na)})
     return res
 

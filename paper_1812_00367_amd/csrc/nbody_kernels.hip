@@ -91,19 +91,33 @@ __device__ __forceinline__ int wave_sum_i32(int v)
     return v;
 }
 
-// 1/sqrt(x) to about one ulp for 2^-126 <= x < 2^128: an FP32 hardware estimate
-// (v_rsq_f32, relative error below 2^-23 measured; it issues in about 2 FP64-FMA
-// slots against 4 for v_rsq_f64, whose estimate is no more accurate), then one
-// third-order correction y (1 + e/2 + 3 e^2 / 8) with e = 1 - x y^2, whose
-// truncation error (5/16) e^3 ~ 2^-67 is far below the FP64 rounding.
-// Callers keep x inside that range: softened squared distances, the masked self
-// pair (1) and the padding records (about 3e36).
+// 1/sqrt(x) to about one ulp: the hardware estimate v_rsq_f64 (relative error
+// below 2^-24 measured on gfx950) followed by one third-order correction
+// y (1 + e/2 + 3 e^2 / 8) with e = 1 - x y^2, whose truncation error (5/16) e^3 is
+// far below the FP64 rounding. (An FP32 estimate is as accurate and measured no
+// faster once the conversions are counted.)
 __device__ __forceinline__ double rsqrt_f64(double x)
 {
-    const double y = (double)__builtin_amdgcn_rsqf((float)x);
+    const double y = __builtin_amdgcn_rsq(x);
     const double e = __builtin_fma(-x, y * y, 1.0);
     const double p = __builtin_fma(e, 0.375, 0.5);
     return __builtin_fma(y, e * p, y);
+}
+
+// Workgroup -> (active-body block, j-split). Workgroups are dispatched to the eight
+// XCDs round-robin (workgroup l on XCD l % 8), each XCD with its own L2. When S is a
+// multiple of 8, a 1-D grid is launched and XCD x is given the contiguous splits
+// [x S/8, (x+1) S/8), so each XCD's L2 fetches only its eighth of the j-stream.
+__device__ __forceinline__ void eval_block_coords(int nsplit, int &ib, int &split)
+{
+    if (gridDim.y == 1 && nsplit > 1) {
+        const int l = blockIdx.x, x = l & 7, k = l >> 3, sx = nsplit >> 3;
+        split = x * sx + k % sx;
+        ib = k / sx;
+    } else {
+        ib = blockIdx.x;
+        split = blockIdx.y;
+    }
 }
 
 // ---------------------------------------------------------------- predictor ----
@@ -275,7 +289,7 @@ __device__ __forceinline__ void interact_f64(I64 &b, const double2 p0, const dou
 template <int IPL, int NW, int TILE>
 __global__ __launch_bounds__(64 * NW) void k_eval_f64(Arrays A, int n, const int32_t *__restrict__ idx,
                                                       int n_act, double eps2, int jchunk,
-                                                      double *__restrict__ part)
+                                                      double *__restrict__ part, int nsplit)
 {
     constexpr int BS = 64 * NW;
     constexpr int CH = TILE * 5;  // 16-byte chunks per tile
@@ -284,10 +298,11 @@ __global__ __launch_bounds__(64 * NW) void k_eval_f64(Arrays A, int n, const int
     __shared__ double2 lds[2][CH];
 
     const int tid = threadIdx.x;
-    const int split = blockIdx.y;
+    int ib, split;
+    eval_block_coords(nsplit, ib, split);
     const int jbeg = split * jchunk;
     const int jend = min(n, jbeg + jchunk);
-    const int ibase = blockIdx.x * (BS * IPL);
+    const int ibase = ib * (BS * IPL);
     const double *__restrict__ jrec = A.jrec;
 
     I64 b[IPL];
@@ -461,7 +476,7 @@ constexpr int kFold = 16;
 template <int IPL, int NW, int TILE>
 __global__ __launch_bounds__(64 * NW) void k_eval_split(Arrays A, int n, const int32_t *__restrict__ idx,
                                                         int n_act, float eps2, int jchunk,
-                                                        double *__restrict__ part)
+                                                        double *__restrict__ part, int nsplit)
 {
     constexpr int BS = 64 * NW;
     constexpr int CH = TILE * 4;  // 16-byte chunks per tile
@@ -471,10 +486,11 @@ __global__ __launch_bounds__(64 * NW) void k_eval_split(Arrays A, int n, const i
     __shared__ float4 lds[2][CH];
 
     const int tid = threadIdx.x;
-    const int split = blockIdx.y;
+    int ib, split;
+    eval_block_coords(nsplit, ib, split);
     const int jbeg = split * jchunk;
     const int jend = min(n, jbeg + jchunk);
-    const int ibase = blockIdx.x * (BS * IPL);
+    const int ibase = ib * (BS * IPL);
     const float *__restrict__ jrec = A.jrec32;
 
     I32 b[IPL];
@@ -1105,13 +1121,16 @@ template <int IPL, int NW, int TILE>
 static hipError_t run_eval(const Arrays &A, const EvalPlan &P, int64_t n, const int32_t *idx,
                            int64_t n_act, double eps, bool split, double *dst, hipStream_t st)
 {
-    const dim3 grid(P.iblocks, P.splits), block(64 * NW);
+    // XCD-aware 1-D grid when the splits divide evenly over the eight XCDs
+    const bool xcd = P.splits > 1 && (P.splits % 8) == 0;
+    const dim3 grid = xcd ? dim3(P.iblocks * P.splits, 1) : dim3(P.iblocks, P.splits);
+    const dim3 block(64 * NW);
     if (split)
         hipLaunchKernelGGL((k_eval_split<IPL, NW, TILE>), grid, block, 0, st, A, (int)n, idx,
-                           (int)n_act, (float)(eps * eps), P.jchunk, dst);
+                           (int)n_act, (float)(eps * eps), P.jchunk, dst, P.splits);
     else
         hipLaunchKernelGGL((k_eval_f64<IPL, NW, TILE>), grid, block, 0, st, A, (int)n, idx,
-                           (int)n_act, eps * eps, P.jchunk, dst);
+                           (int)n_act, eps * eps, P.jchunk, dst, P.splits);
     return hipGetLastError();
 }
 

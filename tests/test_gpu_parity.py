@@ -96,6 +96,26 @@ def test_eval_fp64_every_shape(nb, eps):
     sim.eval_config(None)
 
 
+def test_eval_fp64_xcd_mapping(nb):
+    """Split counts that are multiples of 8 use the XCD-aware 1-D grid."""
+    n = 16401
+    ic, ap = system(n, 111)
+    sim = make_sim(nb, n)
+    sim.set_state(ic.m, ic.x, ic.v, tick0=0, a=ap)
+    sim.predict(0)
+    idx = ni.active_subset(n, 700, 112)
+    ref = oracle.evaluate(ic.m, ic.x, ic.v, ap, 1e-4, idx=idx)
+    for cfg, want in [((2, 4, 256, 8), 8), ((1, 1, 64, 16), 16), ((1, 1, 64, 24), 24),
+                      ((1, 4, 256, 8), 8)]:
+        shape = sim.eval_config(cfg, len(idx))
+        assert shape["splits"] == want, shape
+        got = host(sim.evaluate(idx))
+        errs = eval_errors(got, ref)
+        say("xcd", cfg, errs)
+        assert max(errs) <= TOL_EVAL, (cfg, errs)
+    sim.eval_config(None)
+
+
 def test_eval_tiny_systems(nb):
     # n = 1: no partner, everything zero; n = 2: closed form
     sim = make_sim(nb, 1)

@@ -1,0 +1,136 @@
+"""Split-precision evaluation (float-float coordinate differences, FP32 algebra,
+FP64 accumulation) against the FP64 oracle, and the N = 2^20 Kroupa-mass workload
+on both paths.
+
+The split path cannot meet a 1e-10 relative tolerance: its per-term algebra is
+FP32 (unit roundoff 2^-24 ~ 6e-8). Its bound here is the standard rounding-error
+bound of a sum of terms each computed with a few FP32 roundings and summed in FP32
+blocks of 16 before FP64 accumulation: |q_gpu - q_ref| <= C 2^-24 M, with M the sum
+over j of the magnitude envelope of each term (every sub-term in absolute value)
+and C = 64. The measured relative errors are printed.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import nbody_inputs as ni
+import oracle
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+U32 = 2.0 ** -24
+C_SPLIT = 64.0
+TOL_FP64 = 1e-13
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def nb():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1812_00367_amd as nb
+    return nb
+
+
+def envelope(m, x, v, a, eps, idx, chunk=4096):
+    """Per-body magnitude envelopes M[4][k] (a, j, s, phi) of the pairwise sums."""
+    out = np.zeros((4, len(idx)))
+    n = m.shape[0]
+    for q, i in enumerate(idx):
+        tot = np.zeros(4)
+        for j0 in range(0, n, chunk):
+            sl = slice(j0, min(n, j0 + chunk))
+            r = x[:, sl] - x[:, i:i + 1]
+            dv = v[:, sl] - v[:, i:i + 1]
+            da = a[:, sl] - a[:, i:i + 1]
+            R = (r * r).sum(0) + eps * eps
+            keep = np.arange(j0, sl.stop) != i
+            rn, vn, an = (np.linalg.norm(t, axis=0) for t in (r, dv, da))
+            m3 = m[sl] / R ** 1.5
+            al = np.abs((r * dv).sum(0)) / R
+            be = (vn * vn + rn * an) / R + al * al
+            wn = vn + 3 * al * rn
+            tot += np.array([(m3 * rn)[keep].sum(), (m3 * wn)[keep].sum(),
+                             (m3 * (an + 6 * al * wn + 3 * be * rn))[keep].sum(),
+                             (m[sl] / np.sqrt(R))[keep].sum()])
+        out[:, q] = tot
+    return out
+
+
+def check_split(got, ref, env, label):
+    errs = []
+    for c, c0 in enumerate((0, 3, 6)):
+        d = np.linalg.norm(got[c0:c0 + 3] - ref[c0:c0 + 3], axis=0)
+        rel = d / np.linalg.norm(ref[c0:c0 + 3], axis=0)
+        errs.append(rel)
+        assert np.all(d <= C_SPLIT * U32 * env[c]), (label, c, (d / (U32 * env[c])).max())
+    dphi = np.abs(got[9] - ref[9])
+    assert np.all(dphi <= C_SPLIT * U32 * env[3])
+    say(label, "split rel err a/j/s: p50",
+        [f"{np.median(e):.2e}" for e in errs], "p99", [f"{np.percentile(e, 99):.2e}" for e in errs],
+        "max", [f"{e.max():.2e}" for e in errs])
+    return errs
+
+
+def test_split_every_shape(nb):
+    n = 3001
+    ic = ni.plummer(n, 707)
+    ap = ni.plummer_mean_field_acc(ic.x)
+    eps = 1e-4
+    sim = nb.Simulation(n, eps=eps, precision=nb.NB_SPLIT)
+    sim.set_state(ic.m, ic.x, ic.v, a=ap)
+    sim.predict(0)
+    idx = ni.active_subset(n, 500, 708)
+    ref = oracle.evaluate(ic.m, ic.x, ic.v, ap, eps, idx=idx)
+    env = envelope(ic.m, ic.x, ic.v, ap, eps, idx)
+    for cfg in [(1, 1, 64, 1), (1, 1, 64, 7), (1, 4, 256, 3), (2, 4, 256, 2), (2, 4, 256, 16)]:
+        sim.eval_config(cfg, len(idx))
+        got = sim.evaluate(idx).cpu().numpy()
+        check_split(got, ref, env, f"n=3001 shape={cfg}")
+
+
+def test_split_c2_full_size_sampled(nb):
+    n = 65536
+    ic = ni.plummer(n, 2)
+    ap = ni.plummer_mean_field_acc(ic.x)
+    sim = nb.Simulation(n, eps=1e-4, precision=nb.NB_SPLIT)
+    sim.set_state(ic.m, ic.x, ic.v, a=ap)
+    sim.predict(0)
+    idx = np.arange(n, dtype=np.int32)
+    got = sim.evaluate(idx).cpu().numpy()
+    pick = np.linspace(0, n - 1, 128).astype(np.int32)
+    ref = oracle.evaluate(ic.m, ic.x, ic.v, ap, 1e-4, idx=pick)
+    env = envelope(ic.m, ic.x, ic.v, ap, 1e-4, pick)
+    check_split(got[:, pick], ref, env, "c2 n=65536 all active")
+
+
+@pytest.mark.parametrize("precision", ["fp64", "split"])
+def test_c3_kroupa_2p20_sampled(nb, precision):
+    """N = 2^20 Plummer sphere with Kroupa masses, eps = 1e-4: the 4096-body
+    subsample evaluated against all bodies, 64 of them checked against the oracle."""
+    n = 1 << 20
+    ic = ni.plummer(n, 3, masses=ni.kroupa_masses(n, 3))
+    ap = ni.plummer_mean_field_acc(ic.x)
+    prec = nb.NB_SPLIT if precision == "split" else nb.NB_FP64
+    sim = nb.Simulation(n, eps=1e-4, precision=prec)
+    sim.set_state(ic.m, ic.x, ic.v, a=ap)
+    sim.predict(0)
+    sub = ni.active_subset(n, 4096, 33)
+    got = sim.evaluate(sub).cpu().numpy()
+    pick = np.arange(0, 4096, 64)
+    ref = oracle.evaluate(ic.m, ic.x, ic.v, ap, 1e-4, idx=sub[pick])
+    if precision == "fp64":
+        for c0 in (0, 3, 6):
+            d = np.linalg.norm(got[c0:c0 + 3, pick] - ref[c0:c0 + 3], axis=0)
+            rel = d / np.linalg.norm(ref[c0:c0 + 3], axis=0)
+            say("c3 fp64 rel err", c0, f"max {rel.max():.2e}")
+            assert rel.max() <= TOL_FP64
+    else:
+        env = envelope(ic.m, ic.x, ic.v, ap, 1e-4, sub[pick], chunk=1 << 16)
+        check_split(got[:, pick], ref, env, "c3 n=2^20")
