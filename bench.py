@@ -59,6 +59,9 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--eval-only", type=int, default=0,
                     help="time only K nb_evaluate calls of the full active set (for profiling)")
+    ap.add_argument("--config", choices=("c2", "c3"), default="c2",
+                    help="c2: N=65536 block steps (the headline line); c3: N=2^20 Kroupa-mass "
+                         "sphere, one full evaluation + 16 block steps on both precisions")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run one device-to-device copy of this many MiB (a known-size "
                          "kernel against which HBM byte counters are scaled)")
@@ -80,6 +83,9 @@ def main():
     if not torch.cuda.is_available():
         print("no GPU visible", file=sys.stderr)
         sys.exit(1)
+    if args.config == "c3":
+        print(json.dumps(large_workload()), flush=True)
+        return
     n = args.n
     prec = nb.NB_SPLIT if args.precision == "split" else nb.NB_FP64
     dev = torch.device("cuda", 0)
@@ -232,6 +238,77 @@ def sweep(sim, ic, n, stream, dev, peak):
                     "interactions_per_s": na * n / (med / 1e3),
                     "peak_frac": FLOP_PER_INTERACTION * na * n / (med / 1e3) / 1e12 / peak,
                     "shape": sim.eval_config(None, na)})
+    return res
+
+
+def large_workload(n=1 << 20, steps=16):
+    """Plummer sphere of 2^20 bodies with Kroupa masses (seed 3, eps = 1e-4): Hermite
+    start-up, one timed full evaluation and 16 timed block steps on each precision,
+    with the relative energy drift of each run and the split-vs-FP64 difference of
+    a, j, s on the 4096-body subsample (seed 33)."""
+    import numpy as np
+    import torch
+
+    import nbody_inputs as ni
+    import paper_1812_00367_amd as nb
+    dev = torch.device("cuda", 0)
+    stream = torch.cuda.current_stream(dev)
+    ic = ni.plummer(n, 3, masses=ni.kroupa_masses(n, 3))
+    sub = torch.as_tensor(ni.active_subset(n, 4096, 33), device=dev)
+    allidx = torch.arange(n, dtype=torch.int32, device=dev)
+    res = {"workload": "plummer-2^20 kroupa, full evaluation + 16 block steps", "n": n}
+    subs = {}
+    for name, prec in (("fp64", nb.NB_FP64), ("split", nb.NB_SPLIT)):
+        sim = nb.Simulation(n, eps=EPS, dt_max_log2=DT_MAX, dt_min_log2=DT_MIN, precision=prec,
+                            device=dev)
+        sim.set_state(ic.m, ic.x, ic.v)
+        e0 = sum(sim.energy(0))
+        sim.set_state(ic.m, ic.x, ic.v)
+        sim.start()
+        out = torch.empty((10, n), dtype=torch.float64, device=dev)
+        sim.predict(0)
+        sim.evaluate_into(allidx, out)           # warm-up of the full-N shape
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        sim.evaluate_into(allidx, out)
+        b.record(stream)
+        torch.cuda.synchronize()
+        full_ms = a.elapsed_time(b)
+        subs[name] = sim.evaluate(sub).cpu().numpy()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        inter, tick, done, status, nacts = 0, 0, 0, "ok", []
+        for _ in range(steps):
+            try:
+                na, tick = sim.step()
+            except nb.NBodyError as e:
+                status = f"stopped after {done} block steps: {e}"
+                break
+            inter += na * n
+            nacts.append(na)
+            done += 1
+            print(f"[c3 {name}] block step {done}: n_act={na} t={tick * 2.0 ** DT_MIN:.6e}",
+                  file=sys.stderr, flush=True)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        lv = sim.get_state()["level"]
+        ek, ep = sim.energy(tick) if done else (float("nan"), float("nan"))
+        res[name] = {"full_eval_ms": full_ms,
+                     "full_eval_interactions_per_s": n * n / (full_ms / 1e3),
+                     "block_steps": done, "status": status, "n_act": nacts,
+                     "block_step_interactions": inter,
+                     "block_steps_interactions_per_s": inter / dt if dt > 0 else None,
+                     "time_reached": tick * 2.0 ** DT_MIN,
+                     "max_level": int(lv.max().item()),
+                     "energy_drift": (ek + ep - e0) / abs(e0)}
+        del sim
+    d = {}
+    for c, lab in ((0, "a"), (3, "j"), (6, "s")):
+        ref = subs["fp64"][c:c + 3]
+        rel = np.linalg.norm(subs["split"][c:c + 3] - ref, axis=0) / np.linalg.norm(ref, axis=0)
+        d[lab] = {"p50": float(np.median(rel)), "p99": float(np.percentile(rel, 99)),
+                  "max": float(rel.max())}
+    res["split_vs_fp64_rel_diff"] = d
     return res
 
 

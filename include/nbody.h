@@ -165,14 +165,24 @@ nb_status nb_set_evaluation(nb_ctx *ctx, const int32_t *d_idx, int64_t n_act,
                             const double *d_in);
 
 /* Launch shape of nb_evaluate, for tuning and tests: h_cfg = {bodies per lane
- * (1 or 2), waves per workgroup (1 or 4), LDS tile (64 or 256 bodies), j-splits S
- * (>= 1)}; supported combinations are {2,4,256}, {1,4,256} and {1,1,64}. All zeros
- * (or h_cfg NULL) restores the built-in choice. The shape never changes results
+ * (1 or 2), waves per workgroup, LDS tile (bodies), j-splits S (>= 1)}, with
+ * (waves, tile) one of (1, 64), (1, 128), (2, 128), (1, 256), (2, 256), (4, 256).
+ * All zeros (or h_cfg NULL) returns to the launch table. The shape never changes results
  * beyond FP64 rounding of the split sums. Host-only; returns NB_ERR_ARG for an
  * unsupported combination. h_shape_out (may be NULL) receives the shape the next
  * call with n_act bodies will use: {ipl, waves, tile, jchunk, splits, iblocks}. */
 nb_status nb_eval_config(nb_ctx *ctx, const int32_t *h_cfg, int64_t n_act,
                          int32_t *h_shape_out);
+
+/* Launch-shape table of nb_evaluate, as produced by the tuner
+ * (paper_1812_00367_amd/tune.py): nrows rows of five int32 {n_act_max, bodies per
+ * lane, waves per workgroup, LDS tile, target waves}, n_act_max strictly
+ * increasing. A call with n_act bodies uses the first row with n_act <= n_act_max
+ * (the last row also covers larger sets); the target sets the j-split count
+ * S ~ target / (waves along the active bodies). Supported shapes are those listed
+ * for nb_eval_config. nrows = 0 restores the built-in table. A forced shape from
+ * nb_eval_config takes precedence. Host-only. */
+nb_status nb_eval_table(nb_ctx *ctx, const int32_t *h_rows, int32_t nrows);
 
 /* Hermite 6th-order corrector of the bodies of the last nb_evaluate (same d_idx,
  * n_act) to tick, using that evaluation. Updates x, v, a, j, s, c, a4n, a5n and

@@ -219,6 +219,13 @@ class Simulation:
         self._check(self._lib.nb_eval_config(self._ctx, arr, int(n_act or self.n), shape))
         return dict(zip(("ipl", "waves", "tile", "jchunk", "splits", "iblocks"), list(shape)))
 
+    def eval_table(self, rows=None):
+        """Install a launch-shape table: rows of (n_act_max, ipl, waves, tile, target_waves);
+        None restores the built-in table."""
+        rows = list(rows or [])
+        flat = (ctypes.c_int32 * max(1, 5 * len(rows)))(*[int(v) for r in rows for v in r])
+        self._check(self._lib.nb_eval_table(self._ctx, flat, len(rows)))
+
     def correct(self, idx, tick):
         torch = _torch()
         idx = self._dev(idx, torch.int32, (-1,))

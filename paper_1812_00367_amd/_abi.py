@@ -18,7 +18,7 @@ STATUS_NAMES = {0: "NB_OK", 1: "NB_ERR_ARG", 2: "NB_ERR_SPACE", 3: "NB_ERR_DEVIC
 # Every function the header declares (checked against include/nbody.h by the tests).
 EXPORTS = ["nb_workspace_bytes", "nb_create", "nb_destroy", "nb_last_error", "nb_set_state",
            "nb_set_times", "nb_get_state", "nb_start", "nb_active", "nb_predict", "nb_get_predicted",
-           "nb_evaluate", "nb_set_evaluation", "nb_eval_config", "nb_correct", "nb_timesteps",
+           "nb_evaluate", "nb_set_evaluation", "nb_eval_config", "nb_eval_table", "nb_correct", "nb_timesteps",
            "nb_step", "nb_energy"]
 
 
@@ -78,6 +78,7 @@ def load(path: str = LIB_PATH):
     lib.nb_evaluate.argtypes = [vp, vp, i64, vp]
     lib.nb_set_evaluation.argtypes = [vp, vp, i64, vp]
     lib.nb_eval_config.argtypes = [vp, vp, i64, vp]
+    lib.nb_eval_table.argtypes = [vp, vp, i32]
     lib.nb_correct.argtypes = [vp, vp, i64, i64]
     lib.nb_timesteps.argtypes = [vp, vp, i64, c]
     lib.nb_step.argtypes = [vp, i64, P(i64), P(i64)]
@@ -86,7 +87,6 @@ def load(path: str = LIB_PATH):
         fn = getattr(lib, name)
         if name not in ("nb_destroy", "nb_last_error"):
             fn.restype = c
-    _ = i32
     if path == LIB_PATH:
         _lib = lib
     return lib

@@ -74,7 +74,22 @@ hipError_t launch_get_predicted(const Arrays &A, int64_t n, double *xp, double *
 hipError_t launch_copy_acc_to_jrec(const Arrays &A, int64_t n, bool split, hipStream_t st);
 hipError_t launch_start_store(const Arrays &A, int64_t n, hipStream_t st);
 
-EvalPlan plan_eval(int64_t n, int64_t n_act, int64_t partial_slots, bool split);
+// One row of an evaluation launch table: the shape used for active sets of up to
+// n_act_max bodies; target_waves sets the j-split count S ~ target / (waves along
+// the active bodies).
+struct EvalRow {
+    int n_act_max, ipl, waves, tile, target_waves;
+};
+constexpr int kMaxEvalRows = 32;
+
+// Shapes with a compiled kernel: ipl in {1, 2}; (waves, tile) in {(1, 64), (1, 128),
+// (2, 128), (1, 256), (2, 256), (4, 256)} (a tile's 16-byte chunks split evenly).
+bool eval_shape_supported(int ipl, int waves, int tile);
+// Shape from a table (nrows == 0: the built-in table for the precision).
+EvalPlan plan_eval(int64_t n, int64_t n_act, int64_t partial_slots, bool split,
+                   const EvalRow *rows, int nrows);
+// Shape with a fixed split count S (clamped to the number of tiles).
+EvalPlan plan_eval_fixed(int64_t n, int64_t n_act, int ipl, int waves, int tile, int64_t S);
 hipError_t launch_eval(const Arrays &A, const EvalPlan &P, int64_t n, const int32_t *idx,
                        int64_t n_act, double eps, bool split, double *out, hipStream_t st);
 

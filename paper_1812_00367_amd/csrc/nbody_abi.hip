@@ -29,7 +29,9 @@ struct nb_ctx {
     const int32_t *eval_idx;
     int64_t eval_n;
     bool eval_valid;   // an evaluation is waiting for its correction
-    int32_t cfg[4];    // forced launch shape (all zero: built-in choice)
+    int32_t cfg[4];    // forced launch shape (all zero: use the table)
+    nb::EvalRow rows[nb::kMaxEvalRows];  // launch table (nrows == 0: built-in)
+    int nrows;
 };
 
 namespace {
@@ -165,22 +167,10 @@ nb_status do_predict(nb_ctx *c, int64_t tick)
 
 nb::EvalPlan make_plan(const nb_ctx *c, int64_t n_act)
 {
-    nb::EvalPlan P = nb::plan_eval(c->p.n, n_act, partial_slots_of(&c->p), c->p.precision == NB_SPLIT);
-    if (c->cfg[0]) {
-        P.ipl = c->cfg[0];
-        P.waves = c->cfg[1];
-        P.tile = c->cfg[2];
-        const int64_t per_block = (int64_t)P.ipl * 64 * P.waves;
-        P.iblocks = (int)((n_act + per_block - 1) / per_block);
-        int64_t S = c->cfg[3];
-        const int64_t max_tiles = (c->p.n + P.tile - 1) / P.tile;
-        if (S > max_tiles) S = max_tiles;
-        int64_t per = (c->p.n + S - 1) / S;
-        per = (per + P.tile - 1) / P.tile * P.tile;
-        P.jchunk = (int)per;
-        P.splits = (int)((c->p.n + per - 1) / per);
-    }
-    return P;
+    if (c->cfg[0])
+        return nb::plan_eval_fixed(c->p.n, n_act, c->cfg[0], c->cfg[1], c->cfg[2], c->cfg[3]);
+    return nb::plan_eval(c->p.n, n_act, partial_slots_of(&c->p), c->p.precision == NB_SPLIT,
+                         c->rows, c->nrows);
 }
 
 nb_status do_evaluate(nb_ctx *c, const int32_t *idx, int64_t n_act, double *out)
@@ -198,6 +188,72 @@ nb_status do_evaluate(nb_ctx *c, const int32_t *idx, int64_t n_act, double *out)
 }
 
 }  // namespace
+
+namespace nb {
+
+// Launch shapes. The chip has 256 CUs x 4 SIMDs: a launch wants a few waves per
+// SIMD, while the partial-sum traffic (S x n_act x 80 bytes) stays small against
+// the O(n_act n) arithmetic. The built-in tables were picked by
+// paper_1812_00367_amd/tune.py on an MI355X (N = 65536, both precisions).
+static const EvalRow kDefaultF64[] = {
+    {128, 1, 1, 64, 1024},   {512, 1, 2, 128, 2048},     {2048, 2, 4, 256, 1024},
+    {8192, 2, 4, 256, 4096}, {1 << 30, 2, 4, 256, 8192},
+};
+static const EvalRow kDefaultSplit[] = {
+    {128, 1, 1, 64, 1024},
+    {2048, 1, 2, 128, 2048},
+    {8192, 1, 4, 256, 8192},
+    {1 << 30, 1, 4, 256, 16384},
+};
+
+bool eval_shape_supported(int ipl, int waves, int tile)
+{
+    if (ipl != 1 && ipl != 2)
+        return false;
+    return (waves == 1 && (tile == 64 || tile == 128 || tile == 256)) ||
+           (waves == 2 && (tile == 128 || tile == 256)) || (waves == 4 && tile == 256);
+}
+
+EvalPlan plan_eval_fixed(int64_t n, int64_t n_act, int ipl, int waves, int tile, int64_t S)
+{
+    EvalPlan P{};
+    P.ipl = ipl;
+    P.waves = waves;
+    P.tile = tile;
+    const int64_t per_block = (int64_t)ipl * 64 * waves;
+    P.iblocks = (int)((n_act + per_block - 1) / per_block);
+    const int64_t max_tiles = (n + tile - 1) / tile;
+    if (S > max_tiles) S = max_tiles;
+    if (S < 1) S = 1;
+    int64_t per = (n + S - 1) / S;
+    per = (per + tile - 1) / tile * tile;
+    P.jchunk = (int)per;
+    P.splits = (int)((n + per - 1) / per);
+    return P;
+}
+
+EvalPlan plan_eval(int64_t n, int64_t n_act, int64_t partial_slots, bool split,
+                   const EvalRow *rows, int nrows)
+{
+    if (nrows <= 0) {
+        rows = split ? kDefaultSplit : kDefaultF64;
+        nrows = (int)((split ? sizeof kDefaultSplit : sizeof kDefaultF64) / sizeof(EvalRow));
+    }
+    const EvalRow *r = &rows[nrows - 1];
+    for (int k = 0; k < nrows; ++k)
+        if (n_act <= rows[k].n_act_max) {
+            r = &rows[k];
+            break;
+        }
+    const int64_t per_block = (int64_t)r->ipl * 64 * r->waves;
+    const int64_t waves_i = (n_act + per_block - 1) / per_block * r->waves;
+    int64_t S = (r->target_waves + waves_i - 1) / waves_i;
+    const int64_t cap = partial_slots / (n_act > 0 ? n_act : 1);
+    if (S > cap) S = cap;
+    return plan_eval_fixed(n, n_act, r->ipl, r->waves, r->tile, S);
+}
+
+}  // namespace nb
 
 extern "C" {
 
@@ -435,9 +491,7 @@ nb_status nb_eval_config(nb_ctx *c, const int32_t *h_cfg, int64_t n_act, int32_t
         memcpy(cfg, h_cfg, sizeof cfg);
     const bool zero = !cfg[0] && !cfg[1] && !cfg[2] && !cfg[3];
     if (!zero) {
-        const bool ok = cfg[3] >= 1 && ((cfg[0] == 2 && cfg[1] == 4 && cfg[2] == 256) ||
-                                        (cfg[0] == 1 && cfg[1] == 4 && cfg[2] == 256) ||
-                                        (cfg[0] == 1 && cfg[1] == 1 && cfg[2] == 64));
+        const bool ok = cfg[3] >= 1 && nb::eval_shape_supported(cfg[0], cfg[1], cfg[2]);
         if (!ok)
             return fail(c, NB_ERR_ARG, "unsupported launch shape {%d,%d,%d,%d}", cfg[0], cfg[1],
                         cfg[2], cfg[3]);
@@ -454,6 +508,26 @@ nb_status nb_eval_config(nb_ctx *c, const int32_t *h_cfg, int64_t n_act, int32_t
         h_shape_out[4] = P.splits;
         h_shape_out[5] = P.iblocks;
     }
+    return NB_OK;
+}
+
+nb_status nb_eval_table(nb_ctx *c, const int32_t *h_rows, int32_t nrows)
+{
+    NB_CTX(c);
+    if (nrows < 0 || nrows > nb::kMaxEvalRows || (nrows > 0 && !h_rows))
+        return fail(c, NB_ERR_ARG, "nrows must be in [0, %d]", nb::kMaxEvalRows);
+    for (int k = 0; k < nrows; ++k) {
+        const int32_t *r = h_rows + 5 * k;
+        if (r[0] < 1 || (k > 0 && r[0] <= h_rows[5 * (k - 1)]) || r[4] < 1 ||
+            !nb::eval_shape_supported(r[1], r[2], r[3]))
+            return fail(c, NB_ERR_ARG, "bad table row %d {%d,%d,%d,%d,%d}", k, r[0], r[1], r[2],
+                        r[3], r[4]);
+    }
+    for (int k = 0; k < nrows; ++k) {
+        const int32_t *r = h_rows + 5 * k;
+        c->rows[k] = nb::EvalRow{r[0], r[1], r[2], r[3], r[4]};
+    }
+    c->nrows = nrows;
     return NB_OK;
 }
 

@@ -1086,37 +1086,6 @@ hipError_t launch_start_store(const Arrays &A, int64_t n, hipStream_t st)
     return hipGetLastError();
 }
 
-// Launch shape. The chip has 256 CUs x 4 SIMDs; aim for enough waves to keep
-// every SIMD busy with a few waves while keeping the partial-sum traffic
-// (S x n_act x 80 bytes) small against the O(n_act n) arithmetic.
-EvalPlan plan_eval(int64_t n, int64_t n_act, int64_t partial_slots, bool split)
-{
-    EvalPlan P{};
-    (void)split;
-    const int64_t target_waves = 8192;
-    if (n_act >= 32768) {
-        P.ipl = 2; P.waves = 4; P.tile = 256;
-    } else if (n_act >= 4096) {
-        P.ipl = 1; P.waves = 4; P.tile = 256;
-    } else {
-        P.ipl = 1; P.waves = 1; P.tile = 64;
-    }
-    const int64_t per_block = (int64_t)P.ipl * 64 * P.waves;
-    P.iblocks = (int)((n_act + per_block - 1) / per_block);
-    const int64_t waves_i = (int64_t)P.iblocks * P.waves;
-    int64_t S = (target_waves + waves_i - 1) / waves_i;
-    const int64_t max_tiles = (n + P.tile - 1) / P.tile;
-    if (S > max_tiles) S = max_tiles;
-    const int64_t cap = partial_slots / (n_act > 0 ? n_act : 1);
-    if (S > cap) S = cap;
-    if (S < 1) S = 1;
-    int64_t per = (n + S - 1) / S;
-    per = (per + P.tile - 1) / P.tile * P.tile;
-    P.jchunk = (int)per;
-    P.splits = (int)((n + per - 1) / per);
-    return P;
-}
-
 template <int IPL, int NW, int TILE>
 static hipError_t run_eval(const Arrays &A, const EvalPlan &P, int64_t n, const int32_t *idx,
                            int64_t n_act, double eps, bool split, double *dst, hipStream_t st)
@@ -1141,14 +1110,15 @@ hipError_t launch_eval(const Arrays &A, const EvalPlan &P, int64_t n, const int3
         return hipSuccess;
     double *dst = (P.splits == 1) ? A.evalbuf : A.part;
     hipError_t e;
-    if (P.ipl == 2 && P.waves == 4 && P.tile == 256)
-        e = run_eval<2, 4, 256>(A, P, n, idx, n_act, eps, split, dst, st);
-    else if (P.ipl == 1 && P.waves == 4 && P.tile == 256)
-        e = run_eval<1, 4, 256>(A, P, n, idx, n_act, eps, split, dst, st);
-    else if (P.ipl == 1 && P.waves == 1 && P.tile == 64)
-        e = run_eval<1, 1, 64>(A, P, n, idx, n_act, eps, split, dst, st);
-    else
-        return hipErrorInvalidValue;
+#define NB_SHAPE(I, W, T)                                                                  \
+    else if (P.ipl == I && P.waves == W && P.tile == T) e =                                \
+        run_eval<I, W, T>(A, P, n, idx, n_act, eps, split, dst, st);
+    if (false) e = hipErrorInvalidValue;
+    NB_SHAPE(1, 1, 64) NB_SHAPE(1, 1, 128) NB_SHAPE(1, 2, 128) NB_SHAPE(1, 1, 256)
+    NB_SHAPE(1, 2, 256) NB_SHAPE(1, 4, 256) NB_SHAPE(2, 1, 64) NB_SHAPE(2, 1, 128)
+    NB_SHAPE(2, 2, 128) NB_SHAPE(2, 1, 256) NB_SHAPE(2, 2, 256) NB_SHAPE(2, 4, 256)
+    else return hipErrorInvalidValue;
+#undef NB_SHAPE
     if (e != hipSuccess)
         return e;
     const int64_t count = 10 * n_act;
