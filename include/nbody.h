@@ -206,6 +206,81 @@ nb_status nb_step(nb_ctx *ctx, int64_t tick_limit, int64_t *h_n_act, int64_t *h_
  * E_pot = -1/2 sum_i sum_{j != i} m_i m_j / sqrt(r^2 + eps^2). Waits. */
 nb_status nb_energy(nb_ctx *ctx, int64_t tick, double *h_ekin, double *h_epot);
 
+/* ------------------------------------------------------------ batches ----
+ * Many independent systems ("jobs") of uneven size resident in one workspace and
+ * advanced together. Every nb_batch_step gives each job its own next block step
+ * (its own block time and active set, as nb_step does for one system) with one
+ * kernel launch per step of the cycle for all jobs: the evaluation is one launch
+ * over work items (job, 64-body tile of its active set, chunk of jchunk of its
+ * bodies). A job's arithmetic depends only on its own data and on jchunk, so its
+ * results are bitwise the same alone and in any mix of jobs. Jobs are admitted
+ * into a fixed pool of bodies (first fit): nb_batch_add fails with NB_ERR_SPACE
+ * when the pool, the job table or the work buffers have no room, which is the
+ * admission control of a serving loop. Calls wait for the stream. */
+typedef struct nb_batch nb_batch; /* opaque, library-owned host object */
+
+typedef struct {
+    int64_t capacity;      /* bodies in the pool, 1 <= capacity <= 2^30 */
+    int32_t max_jobs;      /* job-table size, 1 <= max_jobs <= 2^20 */
+    int32_t precision;     /* nb_precision of the evaluation */
+    double eps, eta, eta_init;        /* as in nb_params, shared by every job */
+    int32_t dt_max_log2, dt_min_log2; /* as in nb_params */
+    int32_t jchunk;        /* bodies per j-chunk of a work item, multiple of 64; 0 = 1024 */
+    int32_t reserved;      /* must be 0 */
+    int64_t partial_slots; /* partial-sum buffer in (chunk x active body) units;
+                              0 = max(4 capacity, 2^22) */
+    void *stream;          /* hipStream_t for every launch; NULL = the null stream */
+} nb_batch_params;
+
+/* Workspace bytes for a batch; NB_ERR_ARG for invalid parameters. No device use. */
+nb_status nb_batch_workspace_bytes(const nb_batch_params *p, size_t *h_bytes);
+
+/* Create a batch over d_workspace (caller-owned, 256-byte aligned, at least
+ * nb_batch_workspace_bytes()). The library allocates no device memory; it keeps a
+ * few small pinned host buffers for staging. */
+nb_status nb_batch_create(const nb_batch_params *p, void *d_workspace, size_t bytes,
+                          nb_batch **out);
+
+/* Destroy a batch (NULL accepted). Waits for its stream. */
+void nb_batch_destroy(nb_batch *b);
+
+/* Message of the last error on this batch. */
+const char *nb_batch_last_error(const nb_batch *b);
+
+/* Admit a job of n bodies whose state is src (device arrays of this job's size,
+ * as for nb_set_state; m, x, v required) and which runs until tick_end. Without
+ * src->tick the job starts synchronised at tick0 and the Hermite start-up (two
+ * evaluations and the initial-step rule, as nb_start) runs for it alone; with a
+ * full state it resumes exactly. Writes the job id to *h_job. NB_ERR_SPACE (and
+ * no change) when the pool has no free range of n bodies, the job table is full,
+ * or one evaluation of this job would not fit the work buffers. */
+nb_status nb_batch_add(nb_batch *b, int64_t n, const nb_state *src, int64_t tick0,
+                       int64_t tick_end, int32_t *h_job);
+
+/* Remove a job and free its bodies for later admissions. */
+nb_status nb_batch_remove(nb_batch *b, int32_t job);
+
+/* One block step of every job whose next block time is not beyond its tick_end.
+ * Host outputs indexed by job id (arrays of max_jobs entries, each may be NULL):
+ * the number of bodies the job advanced (0: finished, failed or not present), its
+ * next block time, and its error word (0 ok; 1 a non-finite corrector value;
+ * 2 a body needs a step below dt_min; 3 an inconsistent time or level). A job with
+ * a non-zero error word is not stepped again; the other jobs are unaffected.
+ * *h_interactions = the sum over jobs of n_act x n. */
+nb_status nb_batch_step(nb_batch *b, int64_t *h_n_act, int64_t *h_tick_next,
+                        int32_t *h_job_err, int64_t *h_interactions);
+
+/* Copy a job's state into the non-NULL fields of dst (device arrays of the job's
+ * size, layouts as nb_get_state). */
+nb_status nb_batch_get(nb_batch *b, int32_t job, const nb_state *dst);
+
+/* Energy of one job at tick (its bodies are predicted to tick first). */
+nb_status nb_batch_energy(nb_batch *b, int32_t job, int64_t tick, double *h_ekin,
+                          double *h_epot);
+
+/* Pool offset and size of a job. Host-only. */
+nb_status nb_batch_info(const nb_batch *b, int32_t job, int64_t *h_offset, int64_t *h_n);
+
 #ifdef __cplusplus
 }
 #endif

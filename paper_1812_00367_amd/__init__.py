@@ -21,7 +21,8 @@ import ctypes
 from . import _abi
 from ._abi import NB_FP64, NB_SPLIT, NBodyError
 
-__all__ = ["Simulation", "NBodyError", "NB_FP64", "NB_SPLIT", "workspace_bytes"]
+__all__ = ["Simulation", "Batch", "NBodyError", "NB_FP64", "NB_SPLIT", "workspace_bytes",
+           "batch_workspace_bytes"]
 
 
 def _torch():
@@ -264,3 +265,6 @@ class Simulation:
             if record is not None:
                 record(tn, na)
         return steps, log, inter
+
+
+from .batch import Batch, batch_workspace_bytes  # noqa: E402

@@ -19,7 +19,10 @@ STATUS_NAMES = {0: "NB_OK", 1: "NB_ERR_ARG", 2: "NB_ERR_SPACE", 3: "NB_ERR_DEVIC
 EXPORTS = ["nb_workspace_bytes", "nb_create", "nb_destroy", "nb_last_error", "nb_set_state",
            "nb_set_times", "nb_get_state", "nb_start", "nb_active", "nb_predict", "nb_get_predicted",
            "nb_evaluate", "nb_set_evaluation", "nb_eval_config", "nb_eval_table", "nb_correct", "nb_timesteps",
-           "nb_step", "nb_energy"]
+           "nb_step", "nb_energy",
+           "nb_batch_workspace_bytes", "nb_batch_create", "nb_batch_destroy", "nb_batch_last_error",
+           "nb_batch_add", "nb_batch_remove", "nb_batch_step", "nb_batch_get", "nb_batch_energy",
+           "nb_batch_info"]
 
 
 class Params(ctypes.Structure):
@@ -40,6 +43,23 @@ class Params(ctypes.Structure):
 class State(ctypes.Structure):
     _fields_ = [(name, ctypes.c_void_p) for name in
                 ("m", "x", "v", "a", "j", "s", "c", "a4n", "a5n", "phi", "tick", "level")]
+
+
+class BatchParams(ctypes.Structure):
+    _fields_ = [
+        ("capacity", ctypes.c_int64),
+        ("max_jobs", ctypes.c_int32),
+        ("precision", ctypes.c_int32),
+        ("eps", ctypes.c_double),
+        ("eta", ctypes.c_double),
+        ("eta_init", ctypes.c_double),
+        ("dt_max_log2", ctypes.c_int32),
+        ("dt_min_log2", ctypes.c_int32),
+        ("jchunk", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+        ("partial_slots", ctypes.c_int64),
+        ("stream", ctypes.c_void_p),
+    ]
 
 
 class NBodyError(RuntimeError):
@@ -83,9 +103,21 @@ def load(path: str = LIB_PATH):
     lib.nb_timesteps.argtypes = [vp, vp, i64, c]
     lib.nb_step.argtypes = [vp, i64, P(i64), P(i64)]
     lib.nb_energy.argtypes = [vp, i64, P(dbl), P(dbl)]
+    lib.nb_batch_workspace_bytes.argtypes = [P(BatchParams), P(ctypes.c_size_t)]
+    lib.nb_batch_create.argtypes = [P(BatchParams), vp, ctypes.c_size_t, P(vp)]
+    lib.nb_batch_destroy.argtypes = [vp]
+    lib.nb_batch_destroy.restype = None
+    lib.nb_batch_last_error.argtypes = [vp]
+    lib.nb_batch_last_error.restype = ctypes.c_char_p
+    lib.nb_batch_add.argtypes = [vp, i64, P(State), i64, i64, P(i32)]
+    lib.nb_batch_remove.argtypes = [vp, i32]
+    lib.nb_batch_step.argtypes = [vp, vp, vp, vp, P(i64)]
+    lib.nb_batch_get.argtypes = [vp, i32, P(State)]
+    lib.nb_batch_energy.argtypes = [vp, i32, i64, P(dbl), P(dbl)]
+    lib.nb_batch_info.argtypes = [vp, i32, P(i64), P(i64)]
     for name in EXPORTS:
         fn = getattr(lib, name)
-        if name not in ("nb_destroy", "nb_last_error"):
+        if name not in ("nb_destroy", "nb_last_error", "nb_batch_destroy", "nb_batch_last_error"):
             fn.restype = c
     if path == LIB_PATH:
         _lib = lib

@@ -83,3 +83,49 @@ def test_binding_fails_loudly_without_gpu():
     from paper_1812_00367_amd import Simulation
     with pytest.raises(RuntimeError):
         Simulation(16)
+
+
+def _bparams(**kw):
+    p = dict(capacity=4096, max_jobs=16, precision=0, eps=1e-4, eta=0.45, eta_init=0.01,
+             dt_max_log2=-3, dt_min_log2=-40, jchunk=0, reserved=0, partial_slots=0, stream=None)
+    p.update(kw)
+    return _abi.BatchParams(**p)
+
+
+def test_batch_workspace_bytes_and_argument_checks(lib):
+    out = ctypes.c_size_t(0)
+    assert lib.nb_batch_workspace_bytes(ctypes.byref(_bparams()), ctypes.byref(out)) == 0
+    fp64 = out.value
+    # pool state + j-records + evaluation block + default partial buffer (2^22 slots)
+    assert fp64 >= 4096 * (8 * 19 + 12 + 80 + 80) + 80 * (1 << 22)
+    assert lib.nb_batch_workspace_bytes(ctypes.byref(_bparams(precision=1)), ctypes.byref(out)) == 0
+    assert out.value >= fp64 + 64 * 4096
+    assert lib.nb_batch_workspace_bytes(ctypes.byref(_bparams(partial_slots=1 << 23)),
+                                        ctypes.byref(out)) == 0
+    assert out.value >= fp64 + 80 * (1 << 22)
+    bad = [dict(capacity=0), dict(capacity=(1 << 30) + 1), dict(max_jobs=0),
+           dict(max_jobs=(1 << 20) + 1), dict(eps=-1.0), dict(eta=float("inf")),
+           dict(dt_min_log2=-70), dict(precision=3), dict(jchunk=100), dict(jchunk=-64),
+           dict(reserved=2), dict(partial_slots=-5)]
+    for kw in bad:
+        assert lib.nb_batch_workspace_bytes(ctypes.byref(_bparams(**kw)), ctypes.byref(out)) == 1, kw
+    b = ctypes.c_void_p(0)
+    p = _bparams()
+    assert lib.nb_batch_create(ctypes.byref(p), None, 1 << 30, ctypes.byref(b)) == 1
+    assert lib.nb_batch_create(ctypes.byref(p), ctypes.c_void_p(0x1080), 1 << 30, ctypes.byref(b)) == 1
+    assert lib.nb_batch_create(ctypes.byref(p), ctypes.c_void_p(0x100000), 64, ctypes.byref(b)) == 2
+    assert not b.value
+    lib.nb_batch_destroy(None)
+    assert lib.nb_batch_last_error(None) == b"null batch"
+    assert lib.nb_batch_step(None, None, None, None, None) == 1
+    assert lib.nb_batch_remove(None, 0) == 1
+    assert lib.nb_batch_info(None, 0, None, None) == 1
+
+
+def test_batch_binding_fails_loudly_without_gpu():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is visible")
+    from paper_1812_00367_amd import Batch
+    with pytest.raises(RuntimeError):
+        Batch(64, 2)

@@ -1,0 +1,235 @@
+"""GPU checks of the batch entry points (nb_batch_*): many independent clusters of
+uneven size advanced together, each with its own block steps.
+
+  * every job takes exactly the oracle's block steps (same block times, same active
+    counts, same final levels) and reaches the oracle's positions within 1e-9 and
+    its energy change within 1e-9 of |E| (the criterion of the single-system
+    end-to-end test);
+  * a job's results are bitwise the same alone and in any mix of jobs, at any pool
+    offset, in both precisions;
+  * admission (NB_ERR_SPACE when the pool, the job table or the work buffers have no
+    room), removal and reuse of freed ranges;
+  * resume from a checkpoint taken with nb_batch_get is bitwise exact;
+  * a failing job is flagged in its own error word and the others are unaffected.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import nbody_inputs as ni
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+DT_MIN = -40
+DT_MAX = -3
+L = DT_MAX - DT_MIN
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def nb():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1812_00367_amd as nb
+    return nb
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def make_batch(nb, capacity, max_jobs, **kw):
+    kw.setdefault("eps", 1e-4)
+    return nb.Batch(capacity, max_jobs, dt_max_log2=DT_MAX, dt_min_log2=DT_MIN, **kw)
+
+
+def cluster(n, seed, kroupa=True):
+    m = ni.kroupa_masses(n, seed + 7) if kroupa else None
+    return ni.plummer(n, seed, masses=m)
+
+
+def run_to_end(b):
+    steps, inter, logs = b.run()
+    return steps, inter, logs
+
+
+def states(b, jobs):
+    return {j: {k: host(t) for k, t in b.get(j).items()} for j in jobs}
+
+
+# --------------------------------------------------------------- oracle parity --
+def test_batch_jobs_match_oracle(nb):
+    sizes = [70, 200, 333, 1024, 64, 1]
+    # end times are whole multiples of dt_max, where every body of a job is synchronised
+    ends = [1 << L, 2 << L, 3 << L, 1 << L, 2 << L, 1 << L]
+    ics = [cluster(n, 100 + k) for k, n in enumerate(sizes)]
+    b = make_batch(nb, sum(sizes) + 500, 8)
+    jobs = []
+    for ic, te in zip(ics, ends):
+        jobs.append(b.add(ic.m, ic.x, ic.v, te))
+    e0 = {j: sum(b.energy(j, 0)) if ic.m.size > 1 else 0.0 for j, ic in zip(jobs, ics)}
+    steps, inter, logs = run_to_end(b)
+    say("batch steps", steps, "interactions", inter)
+    st = states(b, jobs)
+    total_inter = 0
+    for j, ic, te in zip(jobs, ics, ends):
+        ost = oracle.State(m=ic.m, x=ic.x, v=ic.v)
+        osteps, ostt, osna, ointer = oracle.integrate(ost, 1e-4, 0.45, 0.01, DT_MAX, DT_MIN, te)
+        gt = np.array([t for t, _ in logs[j]])
+        gn = np.array([k for _, k in logs[j]])
+        say("job", j, "n", ic.m.size, "steps gpu/oracle", len(gt), osteps)
+        assert len(gt) == osteps
+        assert np.array_equal(gt, ostt) and np.array_equal(gn, osna)
+        assert np.all(st[j]["tick"] == te)
+        assert np.array_equal(st[j]["level"], ost.level)
+        dx = np.abs(st[j]["x"] - ost.x).max()
+        assert dx < 1e-9, (j, dx)
+        if ic.m.size > 1:
+            e1 = sum(b.energy(j, te))
+            ro = sum(oracle.energy(ic.m, ic.x, ic.v, 1e-4))
+            r1 = sum(oracle.energy(ost.m, ost.x, ost.v, 1e-4))
+            assert abs((e1 - e0[j]) - (r1 - ro)) < 1e-9 * abs(ro), j
+        total_inter += int(ointer) - 2 * ic.m.size ** 2  # the oracle counts its start-up too
+    assert inter == total_inter
+    # nothing is left to do
+    nact, _, err, it = b.step()
+    assert it == 0 and not any(nact) and not any(err)
+
+
+# ------------------------------------------------------- alone vs mix, bitwise --
+@pytest.mark.parametrize("precision", ["fp64", "split"])
+def test_batch_alone_and_mixed_are_bitwise_equal(nb, precision):
+    prec = nb.NB_FP64 if precision == "fp64" else nb.NB_SPLIT
+    t_end = 1 << (L - 2)
+    target = cluster(777, 5)
+    others = [cluster(n, 200 + n) for n in (300, 1500, 64, 129)]
+    kw = dict(precision=prec, jchunk=256)
+    # alone
+    b1 = make_batch(nb, 777, 1, **kw)
+    j1 = b1.add(target.m, target.x, target.v, t_end)
+    run_to_end(b1)
+    alone = states(b1, [j1])[j1]
+    # mixed: other jobs first so the target sits at a different pool offset, one
+    # other job ends earlier and one is removed mid-run
+    b2 = make_batch(nb, 4096, 8, **kw)
+    oj = [b2.add(ic.m, ic.x, ic.v, t_end if k != 1 else t_end // 2) for k, ic in enumerate(others[:2])]
+    j2 = b2.add(target.m, target.x, target.v, t_end)
+    assert b2.info(j2)[0] != b1.info(j1)[0]
+    for k in range(5):
+        b2.step()
+    b2.remove(oj[0])
+    b2.add(others[2].m, others[2].x, others[2].v, t_end)
+    b2.add(others[3].m, others[3].x, others[3].v, t_end)
+    run_to_end(b2)
+    mixed = states(b2, [j2])[j2]
+    for k in alone:
+        assert np.array_equal(alone[k], mixed[k]), k
+    assert sum(b1.energy(j1, t_end)) == sum(b2.energy(j2, t_end))
+
+
+# ------------------------------------------------------------- admission ------
+def test_batch_admission_remove_and_reuse(nb):
+    b = make_batch(nb, 1000, 3)
+    ics = {n: cluster(n, n) for n in (400, 300, 200, 500, 700, 1001)}
+    t_end = 1 << (L - 6)
+    a = b.add(ics[400].m, ics[400].x, ics[400].v, t_end)
+    c = b.add(ics[300].m, ics[300].x, ics[300].v, t_end)
+    assert b.add(ics[500].m, ics[500].x, ics[500].v, t_end) is None      # 300 bodies free
+    assert b.add(ics[1001].m, ics[1001].x, ics[1001].v, t_end) is None   # above capacity
+    d = b.add(ics[200].m, ics[200].x, ics[200].v, t_end)
+    assert b.add(ics[200].m[:50], ics[200].x[:, :50], ics[200].v[:, :50], t_end) is None  # table full
+    assert (b.info(a), b.info(c), b.info(d)) == ((0, 400), (400, 300), (700, 200))
+    b.step()
+    b.remove(c)
+    with pytest.raises(nb.NBodyError):
+        b.remove(c)
+    assert b.add(ics[500].m, ics[500].x, ics[500].v, t_end) is None      # 300 + 100 not adjacent
+    b.remove(a)                                                          # 0..700 merged
+    e = b.add(ics[700].m, ics[700].x, ics[700].v, t_end)
+    assert b.info(e) == (0, 700)
+    steps, inter, logs = run_to_end(b)
+    assert steps > 0
+    st = b.get(e)
+    tick, level = host(st["tick"]), host(st["level"]).astype(np.int64)
+    # t_end is not a multiple of every step: each body stopped at its last time
+    # not beyond t_end, and its next time is beyond it
+    assert np.all(tick <= t_end) and np.all(tick + (np.int64(1) << (L - level)) > t_end)
+    # a job whose single evaluation cannot fit the partial-sum buffer is refused
+    small = make_batch(nb, 4096, 2, jchunk=64, partial_slots=1000)
+    big = cluster(1024, 3)
+    assert small.add(big.m, big.x, big.v, t_end) is None
+    with pytest.raises(nb.NBodyError):
+        small.get(0)
+
+
+# ------------------------------------------------------------ checkpointing ------
+def test_batch_checkpoint_resume_bitwise(nb):
+    """Run to t_mid, checkpoint with nb_batch_get, resume the checkpoints (full state)
+    in a fresh batch to t_end: bitwise the uninterrupted run to t_end."""
+    t_mid, t_end = 1 << (L - 2), 1 << (L - 1)
+    ics = [cluster(n, 40 + n) for n in (256, 640)]
+    b = make_batch(nb, 2048, 4)
+    jobs = [b.add(ic.m, ic.x, ic.v, t_mid) for ic in ics]
+    run_to_end(b)
+    ck = states(b, jobs)
+    b_res = make_batch(nb, 2048, 4)
+    jr = [b_res.add(s["m"], s["x"], s["v"], t_end, a=s["a"], j=s["j"], s=s["s"], c=s["c"],
+                    a4n=s["a4n"], a5n=s["a5n"], tick=s["tick"], level=s["level"])
+          for s in (ck[j] for j in jobs)]
+    run_to_end(b_res)
+    resumed = states(b_res, jr)
+    b_ref = make_batch(nb, 2048, 4)
+    jref = [b_ref.add(ic.m, ic.x, ic.v, t_end) for ic in ics]
+    run_to_end(b_ref)
+    ref = states(b_ref, jref)
+    for a_, r_ in zip(jr, jref):
+        for k in ("x", "v", "a", "j", "s", "c", "a4n", "a5n", "tick", "level"):
+            assert np.array_equal(resumed[a_][k], ref[r_][k]), k
+
+
+# ------------------------------------------------------------ error isolation ----
+def test_batch_failing_job_is_isolated(nb):
+    t_end = 1 << (L - 3)
+    good = [cluster(n, 60 + n) for n in (128, 500)]
+    # a job with a non-finite velocity: its corrector produces non-finite values
+    bad = cluster(100, 9)
+    bad_v = bad.v.copy()
+    bad_v[1, 17] = np.nan
+    # a tight pair of very heavy bodies: its initial step, eta_init sqrt(|a| / |s|)
+    # ~ 0.01 sqrt(r^3 / M) ~ 3e-13, is below dt_min = 2^-40 ~ 9.1e-13
+    heavy_x = np.array([[-5e-4, 5e-4], [0.0, 0.0], [0.0, 0.0]])
+    heavy_v = np.array([[0.0, 0.0], [0.5, -0.5], [0.0, 0.0]])
+    heavy_m = np.array([1e12, 1e12])
+    b = make_batch(nb, 2048, 6)
+    jg = [b.add(ic.m, ic.x, ic.v, t_end) for ic in good]
+    # the non-finite jerk and snap give the largest step (a non-finite step estimate
+    # counts as no limit), so this job first steps, and fails, at t = dt_max
+    jb = b.add(bad.m, bad.x, bad_v, 1 << L)
+    jh = b.add(heavy_m, heavy_x, heavy_v, 1 << L)
+    errs = {}
+    for _ in range(100000):
+        nact, tnext, err, it = b.step()
+        for j in (jb, jh):
+            if err[j]:
+                errs.setdefault(j, err[j])
+        if not any(nact):
+            break
+    say("error words", errs)
+    assert errs.get(jb, 0) == 1 and errs.get(jh, 0) == 2
+    # the good jobs are bitwise what they are alone
+    mixed = states(b, jg)
+    for ic, j in zip(good, jg):
+        b1 = make_batch(nb, 1024, 1)
+        k = b1.add(ic.m, ic.x, ic.v, t_end)
+        run_to_end(b1)
+        alone = states(b1, [k])[k]
+        for key in alone:
+            assert np.array_equal(alone[key], mixed[j][key]), key
