@@ -59,9 +59,16 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--eval-only", type=int, default=0,
                     help="time only K nb_evaluate calls of the full active set (for profiling)")
-    ap.add_argument("--config", choices=("c2", "c3"), default="c2",
+    ap.add_argument("--config", choices=("c2", "c3", "c4"), default="c2",
                     help="c2: N=65536 block steps (the headline line); c3: N=2^20 Kroupa-mass "
-                         "sphere, one full evaluation + 16 block steps on both precisions")
+                         "sphere, one full evaluation + 16 block steps on both precisions; "
+                         "c4: ensemble of 512 clusters integrated together to t=0.25")
+    ap.add_argument("--clusters", type=int, default=512, help="c4: number of clusters")
+    ap.add_argument("--t-end", type=float, default=0.25, help="c4: end time (multiple of 2^-3)")
+    ap.add_argument("--jchunk", type=int, default=0, help="c4: j-chunk per work item (0 = default)")
+    ap.add_argument("--precisions", default="fp64,split", help="c4: precisions to run")
+    ap.add_argument("--steps-per-call", type=int, default=32,
+                    help="c4: batch steps enqueued per call without a host wait")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run one device-to-device copy of this many MiB (a known-size "
                          "kernel against which HBM byte counters are scaled)")
@@ -85,6 +92,11 @@ def main():
         sys.exit(1)
     if args.config == "c3":
         print(json.dumps(large_workload()), flush=True)
+        return
+    if args.config == "c4":
+        print(json.dumps(ensemble_workload(args.clusters, args.t_end, args.jchunk,
+                                           args.precisions.split(","), args.steps_per_call)),
+              flush=True)
         return
     n = args.n
     prec = nb.NB_SPLIT if args.precision == "split" else nb.NB_FP64
@@ -309,6 +321,97 @@ def large_workload(n=1 << 20, steps=16):
         d[lab] = {"p50": float(np.median(rel)), "p99": float(np.percentile(rel, 99)),
                   "max": float(rel.max())}
     res["split_vs_fp64_rel_diff"] = d
+    return res
+
+
+def ensemble_clusters(count, seed=4, lo=256, hi=16384):
+    """Plummer clusters with N log-uniform in [lo, hi] and Kroupa masses, each from its
+    own seed derived from `seed`."""
+    import nbody_inputs as ni
+    g = ni.rng(seed)
+    out = []
+    for k in range(count):
+        n = ni.log_uniform_n(g, lo, hi)
+        s = int(g.integers(0, 2**31 - 1))
+        out.append(ni.plummer(n, s, masses=ni.kroupa_masses(n, s + 1)))
+    return out
+
+
+def ensemble_workload(count=512, t_end=0.25, jchunk=0, precisions=("fp64", "split"), chunk=32):
+    """Many independent clusters advanced together by the batch entry points, each
+    with its own block steps, to t_end. Reports whole-run interactions/s (start-up
+    excluded, every batch step and its host bookkeeping included), the share of the
+    stated FP64 / FP32 vector peak, and the relative energy drift of every cluster."""
+    import numpy as np
+    import torch
+
+    import paper_1812_00367_amd as nb
+    dev = torch.device("cuda", 0)
+    L = DT_MAX - DT_MIN
+    tick_end = int(round(t_end * 2.0 ** -DT_MIN))
+    if tick_end % (1 << L):
+        raise SystemExit("t_end must be a multiple of 2^-3")
+    ics = ensemble_clusters(count)
+    ns = np.array([ic.m.size for ic in ics], dtype=np.int64)
+    res = {"workload": f"ensemble of {count} plummer clusters, N log-uniform [256, 16384], "
+                       f"kroupa masses, eps=1e-4, to t={t_end}",
+           "clusters": count, "sum_n": int(ns.sum()), "sum_n2": float((ns * ns).sum())}
+    for name in precisions:
+        prec = nb.NB_SPLIT if name == "split" else nb.NB_FP64
+        b = nb.Batch(int(ns.sum()), count, eps=EPS, dt_max_log2=DT_MAX, dt_min_log2=DT_MIN,
+                     precision=prec, jchunk=jchunk, device=dev)
+        t0 = time.perf_counter()
+        jobs = []
+        for ic in ics:
+            j = b.add(ic.m, ic.x, ic.v, tick_end)
+            if j is None:
+                raise SystemExit("ensemble does not fit the batch")
+            jobs.append(j)
+        torch.cuda.synchronize()
+        t_start = time.perf_counter() - t0
+        e0 = np.array([sum(b.energy(j, 0)) for j in jobs])
+        print(f"[c4 {name}] {count} clusters admitted, start-up {t_start:.2f} s", file=sys.stderr,
+              flush=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        steps = inter = 0
+        errs = {}
+        last = t0
+        while True:
+            # `chunk` batch steps per call with no host wait in between; a call whose
+            # steps advance no job means every cluster has reached t_end (or failed)
+            nact, tnext, err, it, taken = b.run_steps(chunk)
+            steps += taken
+            inter += it
+            for j in jobs:
+                if err[j]:
+                    errs[j] = err[j]
+            if taken < chunk:
+                break
+            now = time.perf_counter()
+            if now - last > 20:
+                last = now
+                live = sum(1 for j in jobs if nact[j])
+                print(f"[c4 {name}] batch step {steps}: {live} clusters stepping, "
+                      f"{inter:.3e} interactions, {now - t0:.1f} s", file=sys.stderr, flush=True)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        e1 = np.array([sum(b.energy(j, tick_end)) for j in jobs])
+        de = np.abs((e1 - e0) / np.abs(e0))
+        rate = inter / wall
+        peak = PEAK_FP32_TFLOPS if name == "split" else PEAK_FP64_TFLOPS
+        res[name] = {"wall_s": wall, "startup_s": t_start, "batch_steps": steps, "steps_per_call": chunk,
+                     "interactions": inter, "interactions_per_s": rate,
+                     "tflops_at_79": rate * FLOP_PER_INTERACTION / 1e12,
+                     "peak_frac": rate * FLOP_PER_INTERACTION / (peak * 1e12),
+                     "failed_clusters": len(errs),
+                     "energy_drift": {"p50": float(np.median(de)), "p99": float(np.percentile(de, 99)),
+                                      "max": float(de.max())}}
+        print(f"[c4 {name}] {steps} batch steps, {inter:.3e} interactions in {wall:.1f} s "
+              f"= {rate:.3e}/s", file=sys.stderr, flush=True)
+        b.close()
+        del b
+        torch.cuda.empty_cache()
     return res
 
 

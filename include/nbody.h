@@ -208,27 +208,34 @@ nb_status nb_energy(nb_ctx *ctx, int64_t tick, double *h_ekin, double *h_epot);
 
 /* ------------------------------------------------------------ batches ----
  * Many independent systems ("jobs") of uneven size resident in one workspace and
- * advanced together. Every nb_batch_step gives each job its own next block step
- * (its own block time and active set, as nb_step does for one system) with one
- * kernel launch per step of the cycle for all jobs: the evaluation is one launch
- * over work items (job, 64-body tile of its active set, chunk of jchunk of its
- * bodies). A job's arithmetic depends only on its own data and on jchunk, so its
- * results are bitwise the same alone and in any mix of jobs. Jobs are admitted
- * into a fixed pool of bodies (first fit): nb_batch_add fails with NB_ERR_SPACE
- * when the pool, the job table or the work buffers have no room, which is the
- * admission control of a serving loop. Calls wait for the stream. */
+ * advanced together (block steps as in the paper's section "Code implementation").
+ * A batch step gives each job its own next block step (its own block time and
+ * active set, as nb_step does for one system) with six kernel launches for all
+ * jobs and no host work in between: active sets, prediction, a work split, a
+ * persistent evaluation over work items (job, i-tile of up to 64 active bodies,
+ * j-chunk) in two item classes, and a per-body pass that sums the partials in a
+ * fixed order, corrects and sets the new levels. A job's split depends only on its own (n, n_act) and the
+ * batch constants, so its results are bitwise the same alone and in any mix of jobs.
+ * Jobs are admitted into a fixed pool of bodies (first fit): nb_batch_add fails with
+ * NB_ERR_SPACE when the pool or the job table has no room, which is the admission
+ * control of a serving loop. Every call waits for the stream before it returns. */
 typedef struct nb_batch nb_batch; /* opaque, library-owned host object */
 
 typedef struct {
     int64_t capacity;      /* bodies in the pool, 1 <= capacity <= 2^30 */
-    int32_t max_jobs;      /* job-table size, 1 <= max_jobs <= 2^20 */
+    int32_t max_jobs;      /* job-table size, 1 <= max_jobs <= 65536 */
     int32_t precision;     /* nb_precision of the evaluation */
     double eps, eta, eta_init;        /* as in nb_params, shared by every job */
     int32_t dt_max_log2, dt_min_log2; /* as in nb_params */
-    int32_t jchunk;        /* bodies per j-chunk of a work item, multiple of 64; 0 = 1024 */
-    int32_t reserved;      /* must be 0 */
-    int64_t partial_slots; /* partial-sum buffer in (chunk x active body) units;
-                              0 = max(4 capacity, 2^22) */
+    int32_t jchunk;        /* j-records per lane of a work item (multiple of 64; 0 = 128):
+                              sets a job's j-chunks, S = ceil(n / (jchunk W)) where W lanes
+                              share an active body (W = 64 / next power of two >= n_act for
+                              n_act < 64, else 1) */
+    int32_t items_per_job; /* at most this many work items per job and step come from
+                              j-chunks (an upper bound on S i-tiles; 0 = 2048, <= 16384) */
+    int64_t partial_slots; /* partial-sum buffer in (j-chunk x active body) units; raised to
+                              the bound every step fits, 2 capacity + 128 (items_per_job + 1)
+                              max_jobs; 0 = that bound */
     void *stream;          /* hipStream_t for every launch; NULL = the null stream */
 } nb_batch_params;
 
@@ -269,6 +276,13 @@ nb_status nb_batch_remove(nb_batch *b, int32_t job);
  * *h_interactions = the sum over jobs of n_act x n. */
 nb_status nb_batch_step(nb_batch *b, int64_t *h_n_act, int64_t *h_tick_next,
                         int32_t *h_job_err, int64_t *h_interactions);
+
+/* `steps` batch steps enqueued back to back with no host work or wait in between,
+ * then one wait. Outputs as nb_batch_step for the last step (a job that has finished
+ * reports n_act 0); *h_interactions and *h_steps = interactions and batch steps in
+ * which some job advanced, over the call. */
+nb_status nb_batch_run(nb_batch *b, int32_t steps, int64_t *h_n_act, int64_t *h_tick_next,
+                       int32_t *h_job_err, int64_t *h_interactions, int64_t *h_steps);
 
 /* Copy a job's state into the non-NULL fields of dst (device arrays of the job's
  * size, layouts as nb_get_state). */

@@ -21,7 +21,7 @@ EXPORTS = ["nb_workspace_bytes", "nb_create", "nb_destroy", "nb_last_error", "nb
            "nb_evaluate", "nb_set_evaluation", "nb_eval_config", "nb_eval_table", "nb_correct", "nb_timesteps",
            "nb_step", "nb_energy",
            "nb_batch_workspace_bytes", "nb_batch_create", "nb_batch_destroy", "nb_batch_last_error",
-           "nb_batch_add", "nb_batch_remove", "nb_batch_step", "nb_batch_get", "nb_batch_energy",
+           "nb_batch_add", "nb_batch_remove", "nb_batch_step", "nb_batch_run", "nb_batch_get", "nb_batch_energy",
            "nb_batch_info"]
 
 
@@ -56,7 +56,7 @@ class BatchParams(ctypes.Structure):
         ("dt_max_log2", ctypes.c_int32),
         ("dt_min_log2", ctypes.c_int32),
         ("jchunk", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("items_per_job", ctypes.c_int32),
         ("partial_slots", ctypes.c_int64),
         ("stream", ctypes.c_void_p),
     ]
@@ -112,6 +112,7 @@ def load(path: str = LIB_PATH):
     lib.nb_batch_add.argtypes = [vp, i64, P(State), i64, i64, P(i32)]
     lib.nb_batch_remove.argtypes = [vp, i32]
     lib.nb_batch_step.argtypes = [vp, vp, vp, vp, P(i64)]
+    lib.nb_batch_run.argtypes = [vp, i32, vp, vp, vp, P(i64), P(i64)]
     lib.nb_batch_get.argtypes = [vp, i32, P(State)]
     lib.nb_batch_energy.argtypes = [vp, i32, i64, P(dbl), P(dbl)]
     lib.nb_batch_info.argtypes = [vp, i32, P(i64), P(i64)]

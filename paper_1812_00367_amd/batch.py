@@ -23,11 +23,11 @@ def _ptr(t):
 
 def batch_workspace_bytes(capacity, max_jobs, precision=NB_FP64, eps=1e-4, eta=0.45,
                           eta_init=0.01, dt_max_log2=-3, dt_min_log2=-40, jchunk=0,
-                          partial_slots=0):
+                          items_per_job=0, partial_slots=0):
     lib = _abi.load()
     p = _abi.BatchParams(capacity=capacity, max_jobs=max_jobs, precision=precision, eps=eps,
                          eta=eta, eta_init=eta_init, dt_max_log2=dt_max_log2,
-                         dt_min_log2=dt_min_log2, jchunk=jchunk, reserved=0,
+                         dt_min_log2=dt_min_log2, jchunk=jchunk, items_per_job=items_per_job,
                          partial_slots=partial_slots, stream=None)
     out = ctypes.c_size_t(0)
     rc = lib.nb_batch_workspace_bytes(ctypes.byref(p), ctypes.byref(out))
@@ -40,8 +40,8 @@ class Batch:
     """A pool of `capacity` bodies shared by at most `max_jobs` jobs on one GPU."""
 
     def __init__(self, capacity, max_jobs, eps=1e-4, eta=0.45, eta_init=0.01, dt_max_log2=-3,
-                 dt_min_log2=-40, precision=NB_FP64, jchunk=0, partial_slots=0, device=None,
-                 stream=None):
+                 dt_min_log2=-40, precision=NB_FP64, jchunk=0, items_per_job=0, partial_slots=0,
+                 device=None, stream=None):
         torch = _torch()
         if not torch.cuda.is_available():
             raise RuntimeError("paper_1812_00367_amd needs a ROCm GPU; none is visible")
@@ -59,7 +59,7 @@ class Batch:
             capacity=self.capacity, max_jobs=self.max_jobs, precision=self.precision,
             eps=float(eps), eta=float(eta), eta_init=float(eta_init),
             dt_max_log2=self.dt_max_log2, dt_min_log2=self.dt_min_log2, jchunk=int(jchunk),
-            reserved=0, partial_slots=int(partial_slots),
+            items_per_job=int(items_per_job), partial_slots=int(partial_slots),
             stream=ctypes.c_void_p(self.stream.cuda_stream))
         nbytes = ctypes.c_size_t(0)
         rc = self._lib.nb_batch_workspace_bytes(ctypes.byref(self._params), ctypes.byref(nbytes))
@@ -145,6 +145,15 @@ class Batch:
         self._check(self._lib.nb_batch_step(self._ctx, self._nact, self._tnext, self._err,
                                             ctypes.byref(inter)))
         return list(self._nact), list(self._tnext), list(self._err), inter.value
+
+    def run_steps(self, steps):
+        """`steps` batch steps with no host wait in between (nb_batch_run). Returns
+        (n_act, tick_next, err, interactions, steps_taken); the per-job lists describe
+        the last step."""
+        inter, taken = ctypes.c_int64(0), ctypes.c_int64(0)
+        self._check(self._lib.nb_batch_run(self._ctx, int(steps), self._nact, self._tnext, self._err,
+                                           ctypes.byref(inter), ctypes.byref(taken)))
+        return list(self._nact), list(self._tnext), list(self._err), inter.value, taken.value
 
     def run(self, max_steps=1 << 40, record=None):
         """Batch steps until no job advances. Returns (batch steps, interactions,

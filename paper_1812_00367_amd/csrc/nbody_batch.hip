@@ -1,15 +1,24 @@
 // nbody_batch.hip -- many independent N-body systems ("jobs") of uneven size in one
 // workspace, advanced together: every batch step gives each job its own next block
-// step (its own block time and active set), with one launch per kernel for all jobs.
+// step (its own block time and active set, the block-step scheme of the paper's
+// section "Code implementation"), with a fixed sequence of six launches for all jobs
+// and no host work in between:
 //
-// Pool layout: all jobs' bodies live in one pool of `capacity` bodies (job j owns
-// the contiguous range [off_j, off_j + n_j)); vectors are [3][capacity]
-// structure-of-arrays, the j-records are the same 80-byte (and 64-byte split)
-// records as the single-system path. The evaluation of a batch step is one launch
-// over a list of work items (job, 64-body active tile, j-chunk of `jchunk` bodies);
-// each job's partial sums are added in a fixed order afterwards. A job's arithmetic
-// therefore depends only on its own data and on jchunk, never on the other jobs:
-// its results are bitwise the same alone and in any mix.
+//   k_bact     one workgroup per job: next block time, active list (ascending);
+//   k_bpredict every body of every stepping job to its job's block time;
+//   k_plan     one workgroup: each stepping job's work split and the prefix sums that
+//              place its work items, partial sums and active bodies;
+//   k_beval    persistent waves taking work items (job, i-tile, j-chunk) until none
+//              is left (two launches, one per item class);
+//   k_bfinish  one thread per active body: fixed-order sum of its partials, corrector,
+//              new step level.
+//
+// Pool layout: job j owns the contiguous body range [off_j, off_j + n_j) of a pool of
+// `capacity` bodies; vectors are [3][capacity] structure-of-arrays and the j-records
+// are the 80-byte (and 64-byte split) records of the single-system path.
+//
+// A job's split into work items depends only on its own (N, n_act), and every sum is
+// taken in a fixed order, so its results are bitwise the same alone and in any mix.
 #include "nbody.h"
 #include "nb_device.h"
 #include "nb_internal.h"
@@ -28,7 +37,30 @@ namespace {
 
 enum JobErr : int { kJobOk = 0, kJobNumeric = 1, kJobDtMin = 2, kJobLevel = 3 };
 
-constexpr int kItemTile = 64;  // active bodies per work item (one wave, one per lane)
+constexpr int kItemTile = 64;  // active bodies per work item at most (one wave)
+
+// Per-step header written by k_plan.
+// Work items come in three classes, each taken by its own persistent launch (each
+// needs fewer registers than one kernel holding every sweep):
+//   kClassTile: i-tiles of 64 active bodies of a job with fewer than kWideMin, one per
+//               lane (or W lanes per body for a tail of 9..63), LDS-staged j-tiles;
+//   kClassWide: i-tiles of 128 active bodies of a job with at least kWideMin, two per
+//               lane (half the LDS reads per interaction; FP64 only);
+//   kClassDirect: the tail tile of at most 8 active bodies, whose lanes read their
+//               own records from global memory.
+enum ItemClass : int { kClassTile = 0, kClassWide = 1, kClassDirect = 2, kClasses = 3 };
+
+struct StepHdr {
+    int64_t nitems[kClasses]; // work items of this step per class
+    int64_t ntotal;       // active bodies of this step (all jobs)
+    int64_t pslots;       // partial-sum slots used (x 10 doubles)
+    int64_t inter;        // interactions accumulated over counted steps
+    int64_t steps;        // counted steps in which some job advanced
+    int32_t nplan;        // stepping jobs (entries of the plan)
+    int32_t overflow;     // the partial-sum buffer was too small (never by construction)
+    uint32_t counter[kClasses]; // next work item of each class (persistent evaluation)
+    uint32_t pad[3];
+};
 
 struct Pool {
     double *m, *x, *v, *a, *j, *s, *c, *a4n, *a5n, *phi;
@@ -37,16 +69,17 @@ struct Pool {
     int32_t *body_job;  // job id of every pool slot, -1 when free
     double *jrec;
     float *jrec32;
-    double *evalbuf;    // [10][n_act_j] at 10 * off_j for job j
     int32_t *act;       // job j's active list (pool indices) at off_j
     double *part;
-    // job table
-    int64_t *j_off, *j_n, *j_nact, *j_tnext, *j_tend;
+    int64_t part_cap;   // partial-sum slots
+    // job table (by job id); j_nact, j_tnext and j_err are adjacent (one copy)
+    int64_t *j_off, *j_n, *j_tend;
+    int64_t *j_nact, *j_tnext;
     int32_t *j_err;
-    // per-launch group description (uploaded each batch step)
-    int32_t *items;     // [items_cap][4] = job, i-tile, split, group entry
-    int64_t *g_desc;    // [5][group_cap]: job, pbase, rbase (10 n_act prefix), nbase (n_act prefix), S
-    int64_t *g_desc2;   // the same for the corrector and step levels
+    // plan (by position among the stepping jobs)
+    int32_t *pl_job, *pl_na, *pl_S, *pl_tiles, *pl_jch, *pl_wide;
+    int64_t *pl_item0[kClasses], *pl_act0, *pl_pbase;
+    StepHdr *hdr;
     double *en_bsum;
     Status *status;
 };
@@ -54,39 +87,47 @@ struct Pool {
 // -------------------------------------------------------- active selection ----
 // One workgroup per listed job: tick_next = min over its bodies of t + dt, then the
 // bodies due at tick_next in ascending order into act[off ...]; n_act = 0 when
-// tick_next is beyond the job's end time.
-constexpr int kBS = 256;
+// tick_next is beyond the job's end time or the job has failed.
+constexpr int kBS = 1024;
+constexpr int kBW = kBS / 64;
 
 __global__ __launch_bounds__(kBS) void k_bact(Pool P, const int32_t *__restrict__ jobs, int L)
 {
-    __shared__ int64_t red[kBS / 64];
-    __shared__ int wc[kBS / 64];
+    __shared__ int64_t red[kBW];
+    __shared__ int wc[kBW];
+    __shared__ int sbad[kBW];
     const int job = jobs[blockIdx.x];
     const int64_t off = P.j_off[job], n = P.j_n[job];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     int64_t mn = INT64_MAX;
-    bool badlevel = false;
+    int badlevel = 0;
     for (int64_t k = threadIdx.x; k < n; k += kBS) {
         int lv = P.level[off + k];
         if (lv < 0 || lv > L) {
-            badlevel = true;
+            badlevel = 1;
             lv = L;
         }
         const int64_t e = P.tick[off + k] + ((int64_t)1 << (L - lv));
         mn = e < mn ? e : mn;
     }
-    if (badlevel)
-        P.j_err[job] = kJobLevel;
     mn = wave_min_i64(mn);
-    if (lane == 0)
+    badlevel = wave_max_i32(badlevel);
+    if (lane == 0) {
         red[wave] = mn;
+        sbad[wave] = badlevel;
+    }
     __syncthreads();
+    // every thread takes the same decision from the same shared values
     int64_t tn = red[0];
-    for (int w = 1; w < kBS / 64; ++w)
+    int anybad = sbad[0];
+    for (int w = 1; w < kBW; ++w) {
         tn = red[w] < tn ? red[w] : tn;
-    const bool beyond = tn > P.j_tend[job];
+        anybad |= sbad[w];
+    }
+    const int err0 = P.j_err[job];  // not written by this kernel before its end
+    const bool skip = tn > P.j_tend[job] || err0 != kJobOk || anybad;
     int64_t base = 0;
-    if (!beyond) {
+    if (!skip) {
         for (int64_t r0 = 0; r0 < n; r0 += kBS) {
             const int64_t k = r0 + threadIdx.x;
             bool due = false;
@@ -100,7 +141,7 @@ __global__ __launch_bounds__(kBS) void k_bact(Pool P, const int32_t *__restrict_
                 wc[wave] = __popcll(mask);
             __syncthreads();
             int before = 0, tot = 0;
-            for (int w = 0; w < kBS / 64; ++w) {
+            for (int w = 0; w < kBW; ++w) {
                 before += (w < wave) ? wc[w] : 0;
                 tot += wc[w];
             }
@@ -112,8 +153,201 @@ __global__ __launch_bounds__(kBS) void k_bact(Pool P, const int32_t *__restrict_
     }
     if (threadIdx.x == 0) {
         P.j_tnext[job] = tn;
-        P.j_nact[job] = beyond ? 0 : base;
+        P.j_nact[job] = skip ? 0 : base;
+        if (anybad)
+            P.j_err[job] = kJobLevel;
     }
+}
+
+// ------------------------------------------------------------- work split ----
+// Lanes per active body of an i-tile with `rem` active bodies left: one lane each
+// when rem >= 64 (every lane reads the same j-record: an LDS broadcast), otherwise
+// the P = next power of two >= rem bodies share the wave, W = 64 / P lanes each, and
+// lane w of a body takes records w, w + W, ... so the wave stays full for the
+// one-to-few active bodies typical of a cluster's block steps.
+__host__ __device__ inline int item_lanes(int64_t rem)
+{
+    if (rem >= 64)
+        return 1;
+    int p = 1;
+    while (p < rem)
+        p <<= 1;
+    return 64 / p;
+}
+
+// Split of one job's evaluation: tiles = ceil(n_act / 64) i-tiles (of 128 for a wide
+// job, n_act >= wide_min), S j-chunks of jch bodies. S gives every lane about `lane_recs` records (lane_recs 16 / W when W > 16
+// lanes share a body, so that a job with one to three active bodies still spreads
+// over several waves), but no more chunks than make `target` work items for the job.
+// Depends on (n, n_act) and the batch constants only.
+struct JobSplit {
+    int64_t tiles, S, jch;
+    bool wide;
+};
+
+__host__ __device__ inline JobSplit job_split(int64_t n, int64_t na, int lane_recs, int target,
+                                              int64_t wide_min)
+{
+    JobSplit r;
+    r.wide = na >= wide_min;
+    const int64_t tw = r.wide ? 2 * kItemTile : kItemTile;
+    r.tiles = (na + tw - 1) / tw;
+    const int64_t W = r.wide ? 1 : item_lanes(na < 64 ? na : 64);
+    const int64_t per = (int64_t)lane_recs * (W < 16 ? W : 16);  // bodies per chunk
+    int64_t S = (n + per - 1) / per;
+    const int64_t cap = (target + r.tiles - 1) / r.tiles;
+    S = S < cap ? S : cap;
+    S = S < 1 ? 1 : S;
+    int64_t jch = (n + S - 1) / S;
+    jch = (jch + 63) / 64 * 64;
+    r.jch = jch;
+    r.S = (n + jch - 1) / jch;
+    return r;
+}
+
+// W lanes per body at or above this read their records straight from global memory
+// (the W lanes of a body read W consecutive records per round, one contiguous
+// block): an LDS tile would give each lane too few records to hide the next tile's
+// load.
+constexpr int kDirectW = 8;
+
+// Active bodies from which an FP64 job's tiles hold 128 bodies, two per lane.
+constexpr int64_t kWideMin = 128;
+
+// Whether the last i-tile of a job with na active bodies in `tiles` tiles is taken by
+// the direct class.
+__host__ __device__ inline bool tail_direct(int64_t na, int64_t tiles)
+{
+    return item_lanes(na - (tiles - 1) * kItemTile) >= kDirectW;
+}
+
+// Block-wide exclusive scan of a 64-bit value (kBS threads); returns the exclusive
+// prefix and writes the block total to *total. Uses scr[kBW + 1].
+__device__ __forceinline__ int64_t block_scan(int64_t v, int64_t *scr, int64_t *total)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    int64_t inc = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int64_t u = __shfl_up(inc, o, 64);
+        if (lane >= o)
+            inc += u;
+    }
+    if (lane == 63)
+        scr[wave] = inc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int64_t acc = 0;
+        for (int w = 0; w < kBW; ++w) {
+            const int64_t t = scr[w];
+            scr[w] = acc;
+            acc += t;
+        }
+        scr[kBW] = acc;
+    }
+    __syncthreads();
+    const int64_t ex = scr[wave] + inc - v;
+    *total = scr[kBW];
+    __syncthreads();
+    return ex;
+}
+
+__global__ __launch_bounds__(kBS) void k_plan(Pool P, const int32_t *__restrict__ jobs, int njobs,
+                                              int lane_recs, int target, int64_t wide_min, int count)
+{
+    __shared__ int64_t scr[7][kBW + 1];
+    int64_t c_plan = 0, c_it[kClasses] = {0, 0, 0}, c_act = 0, c_ps = 0, c_inter = 0;
+    for (int base = 0; base < njobs; base += kBS) {
+        const int p = base + (int)threadIdx.x;
+        int job = -1;
+        int64_t na = 0, n = 0;
+        JobSplit sp{0, 0, 0, false};
+        if (p < njobs) {
+            job = jobs[p];
+            na = P.j_nact[job];
+            n = P.j_n[job];
+            if (na > 0)
+                sp = job_split(n, na, lane_recs, target, wide_min);
+        }
+        const bool on = na > 0;
+        // items per class: a wide job's tiles; else full tiles (and a tail of 9..63)
+        // in the tile class and a tail of at most 8 in the direct class
+        const int64_t tail_d = on && !sp.wide && tail_direct(na, sp.tiles) ? 1 : 0;
+        const int64_t n_items[kClasses] = {sp.wide ? 0 : (sp.tiles - tail_d) * sp.S,
+                                           sp.wide ? sp.tiles * sp.S : 0, tail_d * sp.S};
+        int64_t t_plan, t_it[kClasses], x_it[kClasses], t_act, t_ps, t_int;
+        const int64_t x_plan = block_scan(on ? 1 : 0, scr[0], &t_plan);
+        for (int k = 0; k < kClasses; ++k)
+            x_it[k] = block_scan(n_items[k], scr[1 + k], &t_it[k]);
+        const int64_t x_act = block_scan(na, scr[4], &t_act);
+        const int64_t x_ps = block_scan(sp.S * na, scr[5], &t_ps);
+        block_scan(na * n, scr[6], &t_int);
+        if (on) {
+            const int64_t q = c_plan + x_plan;
+            P.pl_job[q] = job;
+            P.pl_na[q] = (int32_t)na;
+            P.pl_S[q] = (int32_t)sp.S;
+            P.pl_tiles[q] = (int32_t)sp.tiles;
+            P.pl_jch[q] = (int32_t)sp.jch;
+            P.pl_wide[q] = sp.wide ? 1 : 0;
+            for (int k = 0; k < kClasses; ++k)
+                P.pl_item0[k][q] = c_it[k] + x_it[k];
+            P.pl_act0[q] = c_act + x_act;
+            P.pl_pbase[q] = 10 * (c_ps + x_ps);
+        }
+        c_plan += t_plan;
+        for (int k = 0; k < kClasses; ++k)
+            c_it[k] += t_it[k];
+        c_act += t_act;
+        c_ps += t_ps;
+        c_inter += t_int;
+    }
+    if (threadIdx.x == 0) {
+        StepHdr *H = P.hdr;
+        const bool over = c_ps > P.part_cap;
+        H->overflow = over ? 1 : H->overflow;
+        H->nplan = over ? 0 : (int32_t)c_plan;
+        for (int k = 0; k < kClasses; ++k) {
+            H->nitems[k] = over ? 0 : c_it[k];
+            H->counter[k] = 0u;
+        }
+        H->ntotal = over ? 0 : c_act;
+        H->pslots = c_ps;
+        if (count && !over) {
+            H->inter += c_inter;
+            H->steps += c_plan > 0 ? 1 : 0;
+        }
+    }
+}
+
+// Largest k in [0, count) with prefix[k] <= e (prefix ascending, prefix[0] = 0).
+template <typename T>
+__device__ __forceinline__ int find_entry(const T *__restrict__ prefix, int count, int64_t e)
+{
+    int lo = 0, hi = count - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (prefix[mid] <= e)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
+// The plan's prefix array in LDS when it has at most kPlanCache entries (a search
+// there costs a few LDS reads instead of a chain of dependent global loads).
+constexpr int kPlanCache = 1024;
+
+__device__ __forceinline__ const int64_t *cache_prefix(const int64_t *__restrict__ g, int count,
+                                                       int64_t *lds)
+{
+    if (count > kPlanCache)
+        return g;
+    for (int k = threadIdx.x; k < count; k += blockDim.x)
+        lds[k] = g[k];
+    __syncthreads();
+    return lds;
 }
 
 // --------------------------------------------------------------- prediction ----
@@ -149,125 +383,501 @@ __global__ __launch_bounds__(256) void k_bpredict_range(Pool P, int64_t cap, int
 }
 
 // --------------------------------------------------------------- evaluation ----
-// One wave per work item (job, i-tile, split): the item's 64 active bodies against
-// the job's j-chunk, partial sums to part[pbase + (s * 10 + c) * n_act + q].
-template <bool SPLIT>
-__global__ __launch_bounds__(64) void k_beval(Pool P, const int32_t *__restrict__ items,
-                                              const int64_t *__restrict__ gd, int ngroup, int jchunk,
-                                              double eps2)
+// A work item of a job: i-tile `tile` (active slots tile*64 ...), j-chunk `sp`
+// (bodies off + sp*jch ... off + min(n, (sp+1) jch)). Items of one j-chunk are
+// adjacent in the item order, so the waves that take them at about the same time
+// share that chunk in L2.
+struct Item {
+    int job, na, ibase, sp, W, lw, w, slot;
+    int64_t off, n, pbase;
+    int jbeg, jend;
+};
+
+template <int CLS>
+__device__ __forceinline__ Item decode_item(const Pool &P, const int64_t *item0, int nplan, int64_t item)
 {
-    constexpr int BS = 64;
-    const int4 it = reinterpret_cast<const int4 *>(items)[blockIdx.x];
-    const int job = it.x, ib = it.y, sp = it.z, gi = it.w;
-    const int64_t off = P.j_off[job], n = P.j_n[job];
-    const int na = (int)P.j_nact[job];
-    const int64_t pbase = gd[1 * ngroup + gi];
-    const int jbeg = (int)(off + (int64_t)sp * jchunk);
-    const int jend = (int)min(off + n, (int64_t)jbeg + jchunk);
-    const int32_t *act = P.act + off;
-    bool bad;
-    int lo, hi;
-    if (SPLIT) {
-        __shared__ float4 lds[2][kItemTile * 4];
-        I32 b[1];
-        load_i_split<1, BS>(P.jrec32, act, na, ib * BS, (int)off, (int)(off + n), b, lo, hi, bad);
-        tiles_split<1, 1, kItemTile>(P.jrec32, jbeg, jend, b, lo, hi, (float)eps2, lds);
-        const int slot = ib * BS + (int)threadIdx.x;
-        if (slot < na)
-            for (int c = 0; c < 10; ++c)
-                P.part[pbase + ((int64_t)sp * 10 + c) * na + slot] = b[0].acc[c];
+    Item it;
+    const int q = find_entry(item0, nplan, item);
+    const int64_t local = item - item0[q];
+    const int tiles = P.pl_tiles[q];
+    it.job = P.pl_job[q];
+    it.na = P.pl_na[q];
+    if constexpr (CLS == kClassDirect) {
+        // the job's last tile, one item per j-chunk
+        it.sp = (int)local;
+        it.ibase = (tiles - 1) * kItemTile;
+    } else if constexpr (CLS == kClassWide) {
+        it.sp = (int)(local / tiles);
+        it.ibase = (int)(local - (int64_t)it.sp * tiles) * 2 * kItemTile;
     } else {
-        __shared__ double2 lds[2][kItemTile * 5];
-        I64 b[1];
-        load_i_f64<1, BS>(P.jrec, act, na, ib * BS, (int)off, (int)(off + n), b, lo, hi, bad);
-        tiles_f64<1, 1, kItemTile>(P.jrec, jbeg, jend, b, lo, hi, eps2, lds);
-        const int slot = ib * BS + (int)threadIdx.x;
-        if (slot < na)
-            for (int c = 0; c < 10; ++c)
-                P.part[pbase + ((int64_t)sp * 10 + c) * na + slot] = b[0].acc[c];
+        const int tiles_a = tiles - (tail_direct(it.na, tiles) ? 1 : 0);
+        it.sp = (int)(local / tiles_a);
+        it.ibase = (int)(local - (int64_t)it.sp * tiles_a) * kItemTile;
     }
+    it.pbase = P.pl_pbase[q];
+    it.off = P.j_off[it.job];
+    it.n = P.j_n[it.job];
+    const int64_t jch = P.pl_jch[q];
+    it.jbeg = (int)(it.off + (int64_t)it.sp * jch);
+    it.jend = (int)min(it.off + it.n, (int64_t)it.jbeg + jch);
+    it.W = CLS == kClassWide ? 1 : item_lanes(it.na - it.ibase);
+    it.lw = __builtin_ctz(it.W);
+    it.w = (int)threadIdx.x & (it.W - 1);
+    it.slot = it.ibase + ((int)threadIdx.x >> it.lw);
+    return it;
+}
+
+constexpr int kStageD = kItemTile * 5 / 64;  // 16-byte chunks per lane per FP64 tile
+constexpr int kStageF = kItemTile * 4 / 64;  // ... per split tile
+
+template <typename T>
+__device__ __forceinline__ T lane_butterfly(T v, int W)
+{
+    for (int o = W >> 1; o > 0; o >>= 1)
+        v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Sum the W lanes of each body in a fixed butterfly and store the item's partial
+// sums at part[pbase + (sp * 10 + c) * na + slot].
+template <typename B>
+__device__ __forceinline__ void finish_item(const Pool &P, B &b, const Item &it, bool bad)
+{
+#pragma unroll
+    for (int c = 0; c < 10; ++c)
+        b.acc[c] = lane_butterfly(b.acc[c], it.W);
+    if (it.w == 0 && it.slot < it.na)
+#pragma unroll
+        for (int c = 0; c < 10; ++c)
+            P.part[it.pbase + ((int64_t)it.sp * 10 + c) * it.na + it.slot] = b.acc[c];
     if (bad)
-        P.j_err[job] = kJobLevel;
+        P.j_err[it.job] = kJobLevel;
 }
 
-// Locate the group entry g with prefix[g] <= e < prefix[g + 1] (prefix ascending,
-// prefix[0] = 0, ngroup entries).
-__device__ __forceinline__ int group_of(const int64_t *__restrict__ prefix, int ngroup, int64_t e)
+// The active body of this lane; an index outside the job's range is replaced by the
+// job's first body and reported through *bad.
+__device__ __forceinline__ int item_body(const Pool &P, const Item &it, bool *bad)
 {
-    int lo = 0, hi = ngroup - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (prefix[mid] <= e)
-            lo = mid;
+    int i = P.act[it.off + (it.slot < it.na ? it.slot : it.na - 1)];
+    *bad = i < it.off || i >= it.off + it.n;
+    return *bad ? (int)it.off : i;
+}
+
+struct Rec64 {
+    double2 p0, p1, p2, p3, p4;
+};
+
+__device__ __forceinline__ Rec64 load_rec64(const double2 *__restrict__ src, int j)
+{
+    const double2 *r = src + (size_t)j * 5;
+    return Rec64{r[0], r[1], r[2], r[3], r[4]};
+}
+
+// Rounds k = 0, 1, ...: lane w takes record jbeg + k W + w. Loads run two rounds
+// ahead. A record past jend is replaced by jbeg's and masked like the self pair (its
+// index set to the lane's own body); masking is used only on rounds that hold the
+// wave's own bodies or the end of the range.
+__device__ __forceinline__ void sweep_direct_f64(const double2 *__restrict__ src, int jbeg, int jend,
+                                                 int W, int w, I64 &b, int lo, int hi, double eps2)
+{
+    const int rounds = (jend - jbeg + W - 1) / W;
+    auto idx = [&](int k) { return jbeg + k * W + w; };
+    auto at = [&](int k) { const int j = idx(k); return j < jend ? j : jbeg; };
+    Rec64 c = load_rec64(src, at(0));
+    Rec64 nx = load_rec64(src, at(rounds > 1 ? 1 : 0));
+    for (int k = 0; k < rounds; ++k) {
+        const Rec64 f = load_rec64(src, at(k + 2 < rounds ? k + 2 : k));
+        const int r0 = jbeg + k * W;
+        if (r0 + W <= jend && (hi < r0 || lo >= r0 + W)) {
+            interact_f64<false>(b, c.p0, c.p1, c.p2, c.p3, c.p4, eps2, 0);
+        } else {
+            const int j = idx(k);
+            interact_f64<true>(b, c.p0, c.p1, c.p2, c.p3, c.p4, eps2, j < jend ? j : b.self);
+        }
+        c = nx;
+        nx = f;
+    }
+}
+
+// LDS tiles of 64 records, double-buffered through registers (as the single-system
+// kernel): lane w reads records w, w + W, ... of each tile.
+__device__ __forceinline__ void sweep_lds_f64(const double2 *__restrict__ src, int jbeg, int jend,
+                                              int W, int lw, int w, I64 &b, int lo, int hi, double eps2,
+                                              double2 (*lds)[kItemTile * 5])
+{
+    const int lane = threadIdx.x;
+    const int ntiles = (jend - jbeg + kItemTile - 1) / kItemTile;
+    double2 stage[kStageD];
+    int valid = 0;
+    auto gload = [&](int t) {
+        const int j0 = jbeg + t * kItemTile;
+        valid = (jend - j0) * 5;
+#pragma unroll
+        for (int c = 0; c < kStageD; ++c) {
+            const int ch = c * 64 + lane;
+            stage[c] = src[ch < valid ? (size_t)j0 * 5 + ch : 0];
+        }
+    };
+    auto lstore = [&](int buf) {
+#pragma unroll
+        for (int c = 0; c < kStageD; ++c) {
+            const int ch = c * 64 + lane;
+            const bool ok = ch < valid;
+            const int part5 = ch % 5;
+            double2 v;
+            v.x = ok ? stage[c].x : (part5 <= 1 ? kFar : 0.0);
+            v.y = ok ? stage[c].y : (part5 == 0 ? kFar : 0.0);
+            lds[buf][ch] = v;
+        }
+    };
+    if (ntiles > 0) {
+        gload(0);
+        lstore(0);
+    }
+    __syncthreads();
+    const int per = kItemTile >> lw;  // records per lane per tile
+    for (int t = 0; t < ntiles; ++t) {
+        const int buf = t & 1;
+        if (t + 1 < ntiles)
+            gload(t + 1);
+        const int j0 = jbeg + t * kItemTile;
+        const double2 *L = lds[buf] + w * 5;
+        const int step = W * 5;
+        if (hi < j0 || lo >= j0 + kItemTile) {
+            double2 p0 = L[0], p1 = L[1], p2 = L[2], p3 = L[3], p4 = L[4];
+            for (int k = 0; k < per; ++k) {
+                const int nx = (k + 1 < per ? k + 1 : k) * step;
+                const double2 n0 = L[nx + 0], n1 = L[nx + 1], n2 = L[nx + 2], n3 = L[nx + 3],
+                              n4 = L[nx + 4];
+                interact_f64<false>(b, p0, p1, p2, p3, p4, eps2, 0);
+                p0 = n0; p1 = n1; p2 = n2; p3 = n3; p4 = n4;
+            }
+        } else {
+            for (int k = 0; k < per; ++k) {
+                const int e = k * step;
+                interact_f64<true>(b, L[e + 0], L[e + 1], L[e + 2], L[e + 3], L[e + 4], eps2,
+                                   j0 + w + k * W);
+            }
+        }
+        if (t + 1 < ntiles)
+            lstore(buf ^ 1);
+        __syncthreads();
+    }
+}
+
+// Persistent: wave b takes item b of its class first, then further items from the
+// step's counter (numbered from the grid size on) until none is left, so the first
+// round needs no atomic and later ones balance uneven item costs.
+template <int CLS>
+__global__ __launch_bounds__(64) void k_beval_f64(Pool P, double eps2)
+{
+    constexpr bool kLds = CLS != kClassDirect;
+    __shared__ double2 lds[kLds ? 2 : 1][kLds ? kItemTile * 5 : 1];
+    __shared__ int64_t s_item0[kPlanCache];
+    const int64_t nitems = P.hdr->nitems[CLS];
+    const int nplan = P.hdr->nplan;
+    if ((int64_t)blockIdx.x >= nitems)  // the other waves drain every item
+        return;
+    const int64_t *item0 = cache_prefix(P.pl_item0[CLS], nplan, s_item0);
+    const double2 *__restrict__ src = reinterpret_cast<const double2 *>(P.jrec);
+    for (int64_t item = blockIdx.x; item < nitems;) {
+        const Item it = decode_item<CLS>(P, item0, nplan, item);
+        if constexpr (CLS == kClassWide) {
+            // two active bodies per lane (slots ibase + lane and ibase + 64 + lane)
+            I64 bw[2];
+            int lo, hi;
+            bool bad;
+            load_i_f64<2, 64>(P.jrec, P.act + it.off, it.na, it.ibase, (int)it.off, (int)(it.off + it.n), bw,
+                              lo, hi, bad);
+            tiles_f64<2, 1, kItemTile>(P.jrec, it.jbeg, it.jend, bw, lo, hi, eps2,
+                                       reinterpret_cast<double2 (*)[kItemTile * 5]>(&lds[0][0]));
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                const int slot = it.ibase + q * 64 + (int)threadIdx.x;
+                if (slot < it.na)
+#pragma unroll
+                    for (int c = 0; c < 10; ++c)
+                        P.part[it.pbase + ((int64_t)it.sp * 10 + c) * it.na + slot] = bw[q].acc[c];
+            }
+            if (bad)
+                P.j_err[it.job] = kJobLevel;
+        } else {
+            bool bad;
+            const int i = item_body(P, it, &bad);
+            I64 b;
+            {
+                const double2 *r = src + (size_t)i * 5;
+                const double2 r0 = r[0], r1 = r[1], r2 = r[2], r3 = r[3], r4 = r[4];
+                b.x[0] = r0.x; b.x[1] = r0.y; b.x[2] = r1.x;
+                b.v[0] = r1.y; b.v[1] = r2.x; b.v[2] = r2.y;
+                b.a[0] = r3.x; b.a[1] = r3.y; b.a[2] = r4.x;
+#pragma unroll
+                for (int c = 0; c < 10; ++c)
+                    b.acc[c] = 0.0;
+                b.self = i;
+            }
+            const int lo = wave_min_i32(i), hi = wave_max_i32(i);
+            if constexpr (CLS == kClassDirect)
+                sweep_direct_f64(src, it.jbeg, it.jend, it.W, it.w, b, lo, hi, eps2);
+            else
+                sweep_lds_f64(src, it.jbeg, it.jend, it.W, it.lw, it.w, b, lo, hi, eps2,
+                              reinterpret_cast<double2 (*)[kItemTile * 5]>(&lds[0][0]));
+            finish_item(P, b, it, bad);
+        }
+        unsigned int got = 0;
+        if (threadIdx.x == 0)
+            got = atomicAdd(&P.hdr->counter[CLS], 1u);
+        item = (int64_t)gridDim.x + (int64_t)__shfl(got, 0, 64);
+    }
+}
+
+// ------------------------------------------------------ split-precision path ----
+struct Rec32 {
+    float4 p0, p1, p2, p3;
+};
+
+__device__ __forceinline__ Rec32 load_rec32(const float4 *__restrict__ src, int j)
+{
+    const float4 *r = src + (size_t)j * 4;
+    return Rec32{r[0], r[1], r[2], r[3]};
+}
+
+__device__ __forceinline__ void fold32(I32 &b)
+{
+#pragma unroll
+    for (int q = 0; q < 10; ++q) {
+        b.acc[q] += (double)b.t[q];
+        b.t[q] = 0.0f;
+    }
+}
+
+// FP32 sums of kFold records of a lane are added into the FP64 accumulators.
+__device__ __forceinline__ void sweep_direct_split(const float4 *__restrict__ src, int jbeg, int jend,
+                                                   int W, int w, I32 &b, int lo, int hi, float eps2)
+{
+    const int rounds = (jend - jbeg + W - 1) / W;
+    auto idx = [&](int k) { return jbeg + k * W + w; };
+    auto at = [&](int k) { const int j = idx(k); return j < jend ? j : jbeg; };
+    Rec32 c = load_rec32(src, at(0));
+    Rec32 nx = load_rec32(src, at(rounds > 1 ? 1 : 0));
+    for (int k = 0; k < rounds; ++k) {
+        const Rec32 f = load_rec32(src, at(k + 2 < rounds ? k + 2 : k));
+        const int r0 = jbeg + k * W;
+        if (r0 + W <= jend && (hi < r0 || lo >= r0 + W)) {
+            interact_f32<false>(b, c.p0, c.p1, c.p2, c.p3, eps2, 0);
+        } else {
+            const int j = idx(k);
+            interact_f32<true>(b, c.p0, c.p1, c.p2, c.p3, eps2, j < jend ? j : b.self);
+        }
+        if (((k + 1) & (kFold - 1)) == 0)
+            fold32(b);
+        c = nx;
+        nx = f;
+    }
+    fold32(b);
+}
+
+__device__ __forceinline__ void sweep_lds_split(const float4 *__restrict__ src, int jbeg, int jend,
+                                                int W, int lw, int w, I32 &b, int lo, int hi, float eps2,
+                                                float4 (*lds)[kItemTile * 4])
+{
+    const int lane = threadIdx.x;
+    const int ntiles = (jend - jbeg + kItemTile - 1) / kItemTile;
+    float4 stage[kStageF];
+    int valid = 0;
+    auto gload = [&](int t) {
+        const int j0 = jbeg + t * kItemTile;
+        valid = (jend - j0) * 4;
+#pragma unroll
+        for (int c = 0; c < kStageF; ++c) {
+            const int ch = c * 64 + lane;
+            stage[c] = src[ch < valid ? (size_t)j0 * 4 + ch : 0];
+        }
+    };
+    auto lstore = [&](int buf) {
+#pragma unroll
+        for (int c = 0; c < kStageF; ++c) {
+            const int ch = c * 64 + lane;
+            const bool ok = ch < valid;
+            const bool first = (ch % 4) == 0;  // padding record {far, far, far, m = 0, 0 ...}
+            float4 v;
+            v.x = ok ? stage[c].x : (first ? 1.0e18f : 0.0f);
+            v.y = ok ? stage[c].y : (first ? 1.0e18f : 0.0f);
+            v.z = ok ? stage[c].z : (first ? 1.0e18f : 0.0f);
+            v.w = ok ? stage[c].w : 0.0f;
+            lds[buf][ch] = v;
+        }
+    };
+    if (ntiles > 0) {
+        gload(0);
+        lstore(0);
+    }
+    __syncthreads();
+    const int per = kItemTile >> lw;
+    const int fold_tiles = per >= kFold ? 1 : kFold / per;
+    for (int t = 0; t < ntiles; ++t) {
+        const int buf = t & 1;
+        if (t + 1 < ntiles)
+            gload(t + 1);
+        const int j0 = jbeg + t * kItemTile;
+        const float4 *L = lds[buf] + w * 4;
+        const int step = W * 4;
+        const bool masked = !(hi < j0 || lo >= j0 + kItemTile);
+        for (int k = 0; k < per; ++k) {
+            const int e = k * step;
+            if (masked)
+                interact_f32<true>(b, L[e + 0], L[e + 1], L[e + 2], L[e + 3], eps2, j0 + w + k * W);
+            else
+                interact_f32<false>(b, L[e + 0], L[e + 1], L[e + 2], L[e + 3], eps2, 0);
+            if (per >= kFold && ((k + 1) & (kFold - 1)) == 0)
+                fold32(b);
+        }
+        if (per < kFold && ((t + 1) % fold_tiles) == 0)
+            fold32(b);
+        if (t + 1 < ntiles)
+            lstore(buf ^ 1);
+        __syncthreads();
+    }
+    fold32(b);
+}
+
+template <int CLS>
+__global__ __launch_bounds__(64) void k_beval_split(Pool P, float eps2)
+{
+    static_assert(CLS != kClassWide, "the split path has no wide class");
+    constexpr bool DIRECT = CLS == kClassDirect;
+    __shared__ float4 lds[DIRECT ? 1 : 2][DIRECT ? 1 : kItemTile * 4];
+    __shared__ int64_t s_item0[kPlanCache];
+    constexpr int cls = CLS;
+    const int64_t nitems = P.hdr->nitems[cls];
+    const int nplan = P.hdr->nplan;
+    if ((int64_t)blockIdx.x >= nitems)  // the other waves drain every item
+        return;
+    const int64_t *item0 = cache_prefix(P.pl_item0[cls], nplan, s_item0);
+    const float4 *__restrict__ src = reinterpret_cast<const float4 *>(P.jrec32);
+    // the first item of each wave is its own index; later ones come from the counter
+    for (int64_t item = blockIdx.x; item < nitems;) {
+        const Item it = decode_item<CLS>(P, item0, nplan, item);
+        bool bad;
+        const int i = item_body(P, it, &bad);
+        I32 b;
+        {
+            const float4 *r = src + (size_t)i * 4;
+            const float4 r0 = r[0], r1 = r[1], r2 = r[2], r3 = r[3];
+            b.xh[0] = r0.x; b.xh[1] = r0.y; b.xh[2] = r0.z;
+            b.xl[0] = r1.x; b.xl[1] = r1.y; b.xl[2] = r1.z;
+            b.v[0] = r2.x; b.v[1] = r2.y; b.v[2] = r2.z;
+            b.a[0] = r3.x; b.a[1] = r3.y; b.a[2] = r3.z;
+#pragma unroll
+            for (int c = 0; c < 10; ++c) {
+                b.acc[c] = 0.0;
+                b.t[c] = 0.0f;
+            }
+            b.self = i;
+        }
+        const int lo = wave_min_i32(i), hi = wave_max_i32(i);
+        if constexpr (DIRECT)
+            sweep_direct_split(src, it.jbeg, it.jend, it.W, it.w, b, lo, hi, eps2);
         else
-            hi = mid - 1;
+            sweep_lds_split(src, it.jbeg, it.jend, it.W, it.lw, it.w, b, lo, hi, eps2,
+                            reinterpret_cast<float4 (*)[kItemTile * 4]>(&lds[0][0]));
+        finish_item(P, b, it, bad);
+        unsigned int got = 0;
+        if (threadIdx.x == 0)
+            got = atomicAdd(&P.hdr->counter[cls], 1u);
+        item = (int64_t)gridDim.x + (int64_t)__shfl(got, 0, 64);
     }
-    return lo;
 }
 
-// Fixed-order sum over each job's S splits into evalbuf[10 off + c n_act + q].
-__global__ __launch_bounds__(256) void k_breduce(Pool P, const int64_t *__restrict__ gd, int ngroup,
-                                                 int64_t total)
-{
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= total)
-        return;
-    const int g = group_of(gd + 2 * ngroup, ngroup, e);
-    const int job = (int)gd[g];
-    const int64_t pbase = gd[1 * ngroup + g], local = e - gd[2 * ngroup + g];
-    const int S = (int)gd[4 * ngroup + g];
-    const int64_t na = P.j_nact[job];
-    double acc = 0.0;
-    for (int s = 0; s < S; ++s)
-        acc += P.part[pbase + (int64_t)s * 10 * na + local];
-    P.evalbuf[10 * P.j_off[job] + local] = acc;
-}
+// ------------------------------------------------- per active body: finishing ----
+// One thread per active body of the step: the fixed-order sum of its S partials, then
+//   kStartA:  the accelerations into the body's j-record (first start-up pass);
+//   kStartB:  a, j, s, phi stored, c = a4 = a5 = 0, initial level (second pass);
+//   kStep:    Hermite corrector over the step, phi and time, new level.
+enum FinishMode : int { kStartA = 0, kStartB = 1, kStep = 2 };
 
-// -------------------------------------------------- corrector and step levels ----
-__global__ __launch_bounds__(256) void k_bcorrect(Pool P, int64_t cap, const int64_t *__restrict__ gd,
-                                                  int ngroup, int64_t total, double tick_size)
+constexpr int kFinLanes = 16;  // lanes that share one body's partial-sum reduction
+
+__global__ __launch_bounds__(256) void k_bfinish(Pool P, int64_t cap, int mode, double tick_size,
+                                                 double eta, double eta_init, int dt_max_log2, int L)
 {
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= total)
+    __shared__ int64_t s_act0[kPlanCache];
+    const int64_t total = P.hdr->ntotal;
+    const int nplan = P.hdr->nplan;
+    constexpr int per_block = 256 / kFinLanes;
+    if ((int64_t)blockIdx.x * per_block >= total)
         return;
-    const int g = group_of(gd + 3 * ngroup, ngroup, e);
-    const int job = (int)gd[g];
-    const int64_t q = e - gd[3 * ngroup + g], off = P.j_off[job], na = P.j_nact[job];
-    const int64_t i = P.act[off + q];
-    const int64_t tn = P.j_tnext[job], ti = P.tick[i];
-    if (ti >= tn) {
-        P.j_err[job] = kJobLevel;
-        return;
+    const int64_t *act0 = cache_prefix(P.pl_act0, nplan, s_act0);
+    const int l = (int)threadIdx.x & (kFinLanes - 1);
+    // every lane of a group runs the same number of iterations (shuffles inside)
+    for (int64_t e0 = (int64_t)blockIdx.x * per_block; e0 < total; e0 += (int64_t)gridDim.x * per_block) {
+        const int64_t e = e0 + (threadIdx.x / kFinLanes);
+        const bool live = e < total;
+        const int q = find_entry(act0, nplan, live ? e : total - 1);
+        const int job = P.pl_job[q];
+        const int64_t slot = (live ? e : total - 1) - act0[q], na = P.pl_na[q], pbase = P.pl_pbase[q];
+        const int S = P.pl_S[q];
+        // lane l sums chunks l, l + 16, ... in ascending order; the 16 lane sums are
+        // then added by a fixed butterfly: one fixed order for a given S
+        double ev[10];
+#pragma unroll
+        for (int c = 0; c < 10; ++c)
+            ev[c] = 0.0;
+        for (int sp = l; sp < S; sp += kFinLanes) {
+            const double *src = P.part + pbase + (int64_t)sp * 10 * na + slot;
+#pragma unroll
+            for (int c = 0; c < 10; ++c)
+                ev[c] += src[(int64_t)c * na];
+        }
+#pragma unroll
+        for (int c = 0; c < 10; ++c)
+            ev[c] = lane_butterfly(ev[c], kFinLanes);
+        if (!live || l != 0)
+            continue;
+        const int64_t off = P.j_off[job];
+        const int64_t i = P.act[off + slot];
+        if (mode == kStartA) {
+            for (int c = 0; c < 3; ++c) {
+                P.jrec[i * kRecD + 6 + c] = ev[c];
+                if (P.jrec32)
+                    P.jrec32[i * kRecF + 12 + c] = (float)ev[c];
+            }
+            continue;
+        }
+        int init = 0;
+        if (mode == kStartB) {
+            for (int c = 0; c < 3; ++c) {
+                P.a[c * cap + i] = ev[0 + c];
+                P.j[c * cap + i] = ev[3 + c];
+                P.s[c * cap + i] = ev[6 + c];
+                P.c[c * cap + i] = 0.0;
+            }
+            P.a4n[i] = 0.0;
+            P.a5n[i] = 0.0;
+            P.phi[i] = ev[9];
+            init = 1;
+        } else {
+            const int64_t tn = P.j_tnext[job], ti = P.tick[i];
+            if (ti >= tn) {
+                P.j_err[job] = kJobLevel;
+                continue;
+            }
+            const bool ok = correct_body(P.x, P.v, P.a, P.j, P.s, P.c, P.a4n, P.a5n, (size_t)cap,
+                                         (size_t)i, ev, 1, (double)(tn - ti) * tick_size);
+            P.phi[i] = ev[9];
+            P.tick[i] = tn;
+            if (!ok)
+                P.j_err[job] = kJobNumeric;
+        }
+        bool dtmin;
+        P.level[i] = level_for_body(P.a, P.j, P.s, P.c, P.a4n, P.a5n, (size_t)cap, (size_t)i, P.tick[i],
+                                    P.level[i], init, eta, eta_init, dt_max_log2, L, &dtmin);
+        if (dtmin)
+            P.j_err[job] = kJobDtMin;
     }
-    const double *ev = P.evalbuf + 10 * off + q;
-    const bool ok = correct_body(P.x, P.v, P.a, P.j, P.s, P.c, P.a4n, P.a5n, (size_t)cap, (size_t)i,
-                                 ev, (size_t)na, (double)(tn - ti) * tick_size);
-    P.phi[i] = ev[9 * na];
-    P.tick[i] = tn;
-    if (!ok)
-        P.j_err[job] = kJobNumeric;
 }
 
-__global__ __launch_bounds__(256) void k_blevels(Pool P, int64_t cap, const int64_t *__restrict__ gd,
-                                                 int ngroup, int64_t total, int init, double eta,
-                                                 double eta_init, int dt_max_log2, int L)
-{
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= total)
-        return;
-    const int g = group_of(gd + 3 * ngroup, ngroup, e);
-    const int job = (int)gd[g];
-    const int64_t i = P.act[P.j_off[job] + (e - gd[3 * ngroup + g])];
-    bool dtmin;
-    P.level[i] = level_for_body(P.a, P.j, P.s, P.c, P.a4n, P.a5n, (size_t)cap, (size_t)i, P.tick[i],
-                                P.level[i], init, eta, eta_init, dt_max_log2, L, &dtmin);
-    if (dtmin)
-        P.j_err[job] = kJobDtMin;
-}
-
-// ------------------------------------------------------------- start-up ----
-// Active list = every body of the job; store the start-up evaluation; copy the
-// first evaluation's accelerations into the predicted records.
+// ------------------------------------------------------------- job set-up ----
 __global__ __launch_bounds__(256) void k_bjob_init(Pool P, int job, int64_t off, int64_t n,
                                                    int64_t tick0)
 {
@@ -283,38 +893,6 @@ __global__ __launch_bounds__(256) void k_bjob_init(Pool P, int job, int64_t off,
         P.act[off + k] = (int32_t)(off + k);
         P.body_job[off + k] = job;
     }
-}
-
-__global__ __launch_bounds__(256) void k_bacc_to_jrec(Pool P, int64_t off, int64_t n, int split)
-{
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= n)
-        return;
-    const int64_t i = off + k;
-    for (int c = 0; c < 3; ++c) {
-        const double a = P.evalbuf[10 * off + (int64_t)c * n + k];
-        P.jrec[i * kRecD + 6 + c] = a;
-        if (split)
-            P.jrec32[i * kRecF + 12 + c] = (float)a;
-    }
-}
-
-__global__ __launch_bounds__(256) void k_bstart_store(Pool P, int64_t cap, int64_t off, int64_t n)
-{
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= n)
-        return;
-    const int64_t i = off + k;
-    const double *e = P.evalbuf + 10 * off;
-    for (int c = 0; c < 3; ++c) {
-        P.a[c * cap + i] = e[(0 + c) * n + k];
-        P.j[c * cap + i] = e[(3 + c) * n + k];
-        P.s[c * cap + i] = e[(6 + c) * n + k];
-        P.c[c * cap + i] = 0.0;
-    }
-    P.phi[i] = e[9 * n + k];
-    P.a4n[i] = 0.0;
-    P.a5n[i] = 0.0;
 }
 
 // Load a job's state from caller arrays laid out [3][n] into the pool ([3][cap]).
@@ -377,6 +955,23 @@ __global__ __launch_bounds__(256) void k_bfree(Pool P, int64_t off, int64_t n)
         P.body_job[off + k] = -1;
 }
 
+__global__ __launch_bounds__(64) void k_hdr_reset(Pool P)
+{
+    if (threadIdx.x == 0) {
+        StepHdr *H = P.hdr;
+        for (int k = 0; k < kClasses; ++k) {
+            H->nitems[k] = 0;
+            H->counter[k] = 0u;
+        }
+        H->ntotal = 0;
+        H->pslots = 0;
+        H->inter = 0;
+        H->steps = 0;
+        H->nplan = 0;
+        H->overflow = 0;
+    }
+}
+
 unsigned nblk(int64_t count, int bs) { return (unsigned)((count + bs - 1) / bs); }
 
 }  // namespace
@@ -388,44 +983,54 @@ struct nb_batch {
     nb_batch_params p;
     hipStream_t st;
     Pool P;
-    int64_t cap, items_cap, group_cap, partial_slots;
+    int64_t cap, partial_slots;
+    int lane_recs, target;
+    int eval_grid[nb::kClasses], finish_grid;
     char msg[512];
     // host job table
     std::vector<int64_t> off, n, tend;
     std::vector<char> alive;
     std::vector<std::pair<int64_t, int64_t>> free_ranges;  // (offset, length), sorted
     // pinned host staging
-    int32_t *h_items;
-    int64_t *h_desc, *h_desc2;
     int64_t *h_scalar;
-    int64_t *h_nact, *h_tnext;
-    int32_t *h_err;
+    char *h_jobblk;     // mirror of j_nact | j_tnext | j_err
+    nb::StepHdr *h_hdr;
     int32_t *h_jobs;
-    int32_t *d_jobs;
+    int32_t *d_jobs, *d_one;
     nb::Status *h_status;
-    hipEvent_t staged;  // recorded after the last copy out of h_items / h_desc
-    bool staged_valid, has_event;
+    bool jobs_dirty;    // the job list changed since it was last uploaded
+    int njobs;
+    int64_t *h_nact() { return reinterpret_cast<int64_t *>(h_jobblk); }
+    int64_t *h_tnext() { return reinterpret_cast<int64_t *>(h_jobblk) + p.max_jobs; }
+    int32_t *h_err() { return reinterpret_cast<int32_t *>(h_jobblk + 16 * (size_t)p.max_jobs); }
 };
 
 namespace {
 
 size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-constexpr int64_t kItemsCap = (int64_t)1 << 20;
+constexpr int kDefaultLaneRecs = 128;
+constexpr int kDefaultTarget = 2048;
+
+int b_lane_recs(const nb_batch_params *p) { return p->jchunk > 0 ? p->jchunk : kDefaultLaneRecs; }
+int b_target(const nb_batch_params *p) { return p->items_per_job > 0 ? p->items_per_job : kDefaultTarget; }
+
+// Partial-sum slots that every step fits by construction: a job with t i-tiles of w
+// (64 or 128) bodies uses S n_act slots with S <= max(1, ceil(target / t)), i.e. at
+// most n_act + w (target + 1).
+int64_t b_partial_bound(const nb_batch_params *p)
+{
+    return 2 * p->capacity + 128 * ((int64_t)b_target(p) + 1) * p->max_jobs;
+}
 
 int64_t b_partial_slots(const nb_batch_params *p)
 {
-    if (p->partial_slots > 0)
-        return p->partial_slots;
-    const int64_t a = 4 * p->capacity, b = (int64_t)1 << 22;
-    return a > b ? a : b;
+    const int64_t need = b_partial_bound(p);
+    return p->partial_slots > need ? p->partial_slots : need;
 }
 
-int b_jchunk(const nb_batch_params *p) { return p->jchunk > 0 ? p->jchunk : 1024; }
-
 // device workspace layout; returns bytes (base may be null to measure)
-size_t b_layout(const nb_batch_params *p, Pool *P, int32_t **d_jobs, int64_t *items_cap,
-                int64_t *group_cap, char *base)
+size_t b_layout(const nb_batch_params *p, Pool *P, int32_t **d_jobs, int32_t **d_one, char *base)
 {
     const size_t cap = (size_t)p->capacity, J = (size_t)p->max_jobs;
     size_t off = 0;
@@ -437,10 +1042,6 @@ size_t b_layout(const nb_batch_params *p, Pool *P, int32_t **d_jobs, int64_t *it
     };
     const bool split = p->precision == NB_SPLIT;
     const int64_t ps = b_partial_slots(p);
-    // work items per launch (a batch step with more is split over several launches;
-    // one job's full evaluation must fit on its own)
-    *items_cap = kItemsCap;
-    *group_cap = (int64_t)J;
     P->m = (double *)take(8 * cap);
     P->x = (double *)take(24 * cap);
     P->v = (double *)take(24 * cap);
@@ -456,21 +1057,31 @@ size_t b_layout(const nb_batch_params *p, Pool *P, int32_t **d_jobs, int64_t *it
     P->body_job = (int32_t *)take(4 * cap);
     P->jrec = (double *)take(8 * nb::kRecD * cap);
     P->jrec32 = split ? (float *)take(4 * nb::kRecF * cap) : nullptr;
-    P->evalbuf = (double *)take(80 * cap);
     P->act = (int32_t *)take(4 * cap);
     P->part = (double *)take(80 * (size_t)ps);
+    P->part_cap = ps;
     P->j_off = (int64_t *)take(8 * J);
     P->j_n = (int64_t *)take(8 * J);
-    P->j_nact = (int64_t *)take(8 * J);
-    P->j_tnext = (int64_t *)take(8 * J);
     P->j_tend = (int64_t *)take(8 * J);
-    P->j_err = (int32_t *)take(4 * J);
-    P->items = (int32_t *)take(16 * (size_t)*items_cap);
-    P->g_desc = (int64_t *)take(8 * 5 * (size_t)*group_cap);
-    P->g_desc2 = (int64_t *)take(8 * 5 * (size_t)*group_cap);
+    char *blk = (char *)take(20 * J);
+    P->j_nact = (int64_t *)blk;
+    P->j_tnext = blk ? (int64_t *)(blk + 8 * J) : nullptr;
+    P->j_err = blk ? (int32_t *)(blk + 16 * J) : nullptr;
+    P->pl_job = (int32_t *)take(4 * J);
+    P->pl_na = (int32_t *)take(4 * J);
+    P->pl_S = (int32_t *)take(4 * J);
+    P->pl_tiles = (int32_t *)take(4 * J);
+    P->pl_jch = (int32_t *)take(4 * J);
+    for (int k = 0; k < nb::kClasses; ++k)
+        P->pl_item0[k] = (int64_t *)take(8 * J);
+    P->pl_wide = (int32_t *)take(4 * J);
+    P->pl_act0 = (int64_t *)take(8 * J);
+    P->pl_pbase = (int64_t *)take(8 * J);
+    P->hdr = (nb::StepHdr *)take(sizeof(nb::StepHdr));
     P->en_bsum = (double *)take(16 * (size_t)nb::en_blocks(p->capacity));
     P->status = (nb::Status *)take(sizeof(nb::Status));
     *d_jobs = (int32_t *)take(4 * J);
+    *d_one = (int32_t *)take(4);
     return al256(off);
 }
 
@@ -496,7 +1107,7 @@ const char *b_check_params(const nb_batch_params *p)
 {
     if (!p) return "params is NULL";
     if (p->capacity < 1 || p->capacity > ((int64_t)1 << 30)) return "capacity must be in [1, 2^30]";
-    if (p->max_jobs < 1 || p->max_jobs > (1 << 20)) return "max_jobs must be in [1, 2^20]";
+    if (p->max_jobs < 1 || p->max_jobs > (1 << 16)) return "max_jobs must be in [1, 65536]";
     if (!(p->eps >= 0.0) || !isfinite(p->eps)) return "eps must be finite and >= 0";
     if (!(p->eta > 0.0) || !isfinite(p->eta) || !(p->eta_init > 0.0) || !isfinite(p->eta_init))
         return "eta and eta_init must be finite and > 0";
@@ -504,131 +1115,89 @@ const char *b_check_params(const nb_batch_params *p)
     const int L = p->dt_max_log2 - p->dt_min_log2;
     if (L < 0 || L > 62) return "need 0 <= dt_max_log2 - dt_min_log2 <= 62";
     if (p->precision != NB_FP64 && p->precision != NB_SPLIT) return "precision must be NB_FP64 or NB_SPLIT";
-    if (p->jchunk < 0 || (p->jchunk % nb::kItemTile) != 0) return "jchunk must be a multiple of 64 (0 = default)";
-    if (p->reserved != 0) return "reserved must be 0";
+    if (p->jchunk < 0 || p->jchunk > (1 << 20) || (p->jchunk % nb::kItemTile) != 0)
+        return "jchunk must be a multiple of 64 in [0, 2^20] (0 = default)";
+    if (p->items_per_job < 0 || p->items_per_job > (1 << 14))
+        return "items_per_job must be in [0, 16384] (0 = default)";
     if (p->partial_slots < 0) return "partial_slots must be >= 0";
     return nullptr;
 }
 
-// Evaluate the active sets of `group` (jobs with n_act > 0, in the host arrays
-// b->h_nact), in launches that fit the partial and item buffers; results land in
-// each job's evaluation block. Host arrays hold n_act of every listed job.
-nb_status b_evaluate(nb_batch *b, const std::vector<int> &group)
+// Launches of one evaluation over the jobs in `list` (n_list entries, device array)
+// whose n_act is in j_nact, then the finishing pass in `mode`. No host work between.
+nb_status b_eval_finish(nb_batch *b, const int32_t *list, int n_list, int mode, int count)
 {
-    const int jchunk = b_jchunk(&b->p);
-    const int64_t ps = b->partial_slots;
-    const double eps2 = b->p.eps * b->p.eps;
-    size_t k = 0;
-    while (k < group.size()) {
-        // take jobs while the items and partials fit
-        int64_t nitems = 0, pslots = 0;
-        size_t e = k;
-        std::vector<int> gj;
-        while (e < group.size()) {
-            const int job = group[e];
-            const int64_t na = b->h_nact[job];
-            const int64_t S = (b->n[job] + jchunk - 1) / jchunk;
-            const int64_t it = (na + nb::kItemTile - 1) / nb::kItemTile * S;
-            if (S * na > ps)
-                return bfail(b, NB_ERR_SPACE, "job %d needs %lld partial slots (capacity %lld)", job,
-                             (long long)(S * na), (long long)ps);
-            if (!gj.empty() && (nitems + it > b->items_cap || pslots + S * na > ps ||
-                                (int64_t)gj.size() >= b->group_cap))
-                break;
-            if (it > b->items_cap)
-                return bfail(b, NB_ERR_SPACE, "job %d needs %lld work items", job, (long long)it);
-            gj.push_back(job);
-            nitems += it;
-            pslots += S * na;
-            ++e;
-        }
-        const int ng = (int)gj.size();
-        // the previous launch's copies out of the staging buffers must have run
-        if (b->staged_valid)
-            B_HIP(b, hipEventSynchronize(b->staged));
-        int64_t pbase = 0, rbase = 0, nbase = 0, w = 0;
-        for (int g = 0; g < ng; ++g) {
-            const int job = gj[g];
-            const int64_t na = b->h_nact[job];
-            const int64_t S = (b->n[job] + jchunk - 1) / jchunk;
-            b->h_desc[0 * ng + g] = job;
-            b->h_desc[1 * ng + g] = pbase;
-            b->h_desc[2 * ng + g] = rbase;
-            b->h_desc[3 * ng + g] = nbase;
-            b->h_desc[4 * ng + g] = S;
-            const int64_t tiles = (na + nb::kItemTile - 1) / nb::kItemTile;
-            for (int64_t t = 0; t < tiles; ++t)
-                for (int64_t s = 0; s < S; ++s) {
-                    int32_t *it = b->h_items + 4 * w++;
-                    it[0] = job;
-                    it[1] = (int32_t)t;
-                    it[2] = (int32_t)s;
-                    it[3] = g;
-                }
-            pbase += S * 10 * na;
-            rbase += 10 * na;
-            nbase += na;
-        }
-        B_HIP(b, hipMemcpyAsync(b->P.items, b->h_items, 16 * (size_t)w, hipMemcpyHostToDevice, b->st));
-        B_HIP(b, hipMemcpyAsync(b->P.g_desc, b->h_desc, 8 * 5 * (size_t)ng, hipMemcpyHostToDevice, b->st));
-        B_HIP(b, hipEventRecord(b->staged, b->st));
-        b->staged_valid = true;
-        if (b->p.precision == NB_SPLIT)
-            hipLaunchKernelGGL(nb::k_beval<true>, dim3((unsigned)w), dim3(64), 0, b->st, b->P,
-                               (const int32_t *)b->P.items, (const int64_t *)b->P.g_desc, ng, jchunk, eps2);
-        else
-            hipLaunchKernelGGL(nb::k_beval<false>, dim3((unsigned)w), dim3(64), 0, b->st, b->P,
-                               (const int32_t *)b->P.items, (const int64_t *)b->P.g_desc, ng, jchunk, eps2);
-        B_HIP(b, hipGetLastError());
-        hipLaunchKernelGGL(nb::k_breduce, dim3(nb::nblk(rbase, 256)), dim3(256), 0, b->st, b->P,
-                           (const int64_t *)b->P.g_desc, ng, rbase);
-        B_HIP(b, hipGetLastError());
-        k = e;
-    }
-    return NB_OK;
-}
-
-// corrector + levels for a group described in g_desc (already uploaded)
-nb_status b_correct_levels(nb_batch *b, const std::vector<int> &group, int init)
-{
-    // corrector and levels are launched once per group of at most group_cap jobs
-    const double tick_size = ldexp(1.0, b->p.dt_min_log2);
+    const bool split = b->p.precision == NB_SPLIT;
     const int L = b->p.dt_max_log2 - b->p.dt_min_log2;
-    size_t k = 0;
-    while (k < group.size()) {
-        const int ng = (int)std::min<size_t>(group.size() - k, (size_t)b->group_cap);
-        int64_t nbase = 0;
-        for (int g = 0; g < ng; ++g) {
-            const int job = group[k + g];
-            b->h_desc2[0 * ng + g] = job;
-            b->h_desc2[1 * ng + g] = 0;
-            b->h_desc2[2 * ng + g] = 0;
-            b->h_desc2[3 * ng + g] = nbase;
-            b->h_desc2[4 * ng + g] = 0;
-            nbase += b->h_nact[job];
-        }
-        B_HIP(b, hipMemcpyAsync(b->P.g_desc2, b->h_desc2, 8 * 5 * (size_t)ng, hipMemcpyHostToDevice, b->st));
-        if (!init)
-            hipLaunchKernelGGL(nb::k_bcorrect, dim3(nb::nblk(nbase, 256)), dim3(256), 0, b->st, b->P,
-                               b->cap, (const int64_t *)b->P.g_desc2, ng, nbase, tick_size);
-        hipLaunchKernelGGL(nb::k_blevels, dim3(nb::nblk(nbase, 256)), dim3(256), 0, b->st, b->P, b->cap,
-                           (const int64_t *)b->P.g_desc2, ng, nbase, init, b->p.eta, b->p.eta_init,
-                           b->p.dt_max_log2, L);
-        B_HIP(b, hipGetLastError());
-        B_HIP(b, hipStreamSynchronize(b->st));
-        k += ng;
+    // the wide class (two bodies per lane) is FP64 only
+    const int64_t wide_min = split ? INT64_MAX : nb::kWideMin;
+    hipLaunchKernelGGL(nb::k_plan, dim3(1), dim3(nb::kBS), 0, b->st, b->P, list, n_list, b->lane_recs,
+                       b->target, wide_min, count);
+    if (split) {
+        const float e2 = (float)(b->p.eps * b->p.eps);
+        hipLaunchKernelGGL(nb::k_beval_split<nb::kClassTile>, dim3(b->eval_grid[nb::kClassTile]), dim3(64), 0,
+                           b->st, b->P, e2);
+        hipLaunchKernelGGL(nb::k_beval_split<nb::kClassDirect>, dim3(b->eval_grid[nb::kClassDirect]), dim3(64),
+                           0, b->st, b->P, e2);
+    } else {
+        const double e2 = b->p.eps * b->p.eps;
+        hipLaunchKernelGGL(nb::k_beval_f64<nb::kClassWide>, dim3(b->eval_grid[nb::kClassWide]), dim3(64), 0,
+                           b->st, b->P, e2);
+        hipLaunchKernelGGL(nb::k_beval_f64<nb::kClassTile>, dim3(b->eval_grid[nb::kClassTile]), dim3(64), 0,
+                           b->st, b->P, e2);
+        hipLaunchKernelGGL(nb::k_beval_f64<nb::kClassDirect>, dim3(b->eval_grid[nb::kClassDirect]), dim3(64),
+                           0, b->st, b->P, e2);
     }
+    hipLaunchKernelGGL(nb::k_bfinish, dim3(b->finish_grid), dim3(256), 0, b->st, b->P, b->cap, mode,
+                       ldexp(1.0, b->p.dt_min_log2), b->p.eta, b->p.eta_init, b->p.dt_max_log2, L);
+    B_HIP(b, hipGetLastError());
     return NB_OK;
 }
 
-nb_status b_fetch_jobs(nb_batch *b)
+// One block step of every job in the batch, enqueued without waiting.
+nb_status b_enqueue_step(nb_batch *b)
+{
+    if (b->jobs_dirty) {
+        b->njobs = 0;
+        for (int k = 0; k < b->p.max_jobs; ++k)
+            if (b->alive[k])
+                b->h_jobs[b->njobs++] = k;
+        if (b->njobs > 0)
+            B_HIP(b, hipMemcpyAsync(b->d_jobs, b->h_jobs, 4 * (size_t)b->njobs, hipMemcpyHostToDevice, b->st));
+        b->jobs_dirty = false;
+    }
+    if (b->njobs == 0)
+        return NB_OK;
+    const bool split = b->p.precision == NB_SPLIT;
+    hipLaunchKernelGGL(nb::k_bact, dim3(b->njobs), dim3(nb::kBS), 0, b->st, b->P, (const int32_t *)b->d_jobs,
+                       b->p.dt_max_log2 - b->p.dt_min_log2);
+    hipLaunchKernelGGL(nb::k_bpredict, dim3(nb::nblk(b->cap, 256)), dim3(256), 0, b->st, b->P, b->cap,
+                       ldexp(1.0, b->p.dt_min_log2), (int)split);
+    B_HIP(b, hipGetLastError());
+    return b_eval_finish(b, b->d_jobs, b->njobs, nb::kStep, 1);
+}
+
+// Job table and step header to the host (one wait).
+nb_status b_fetch(nb_batch *b)
 {
     const size_t J = (size_t)b->p.max_jobs;
-    B_HIP(b, hipMemcpyAsync(b->h_nact, b->P.j_nact, 8 * J, hipMemcpyDeviceToHost, b->st));
-    B_HIP(b, hipMemcpyAsync(b->h_tnext, b->P.j_tnext, 8 * J, hipMemcpyDeviceToHost, b->st));
-    B_HIP(b, hipMemcpyAsync(b->h_err, b->P.j_err, 4 * J, hipMemcpyDeviceToHost, b->st));
+    B_HIP(b, hipMemcpyAsync(b->h_jobblk, b->P.j_nact, 20 * J, hipMemcpyDeviceToHost, b->st));
+    B_HIP(b, hipMemcpyAsync(b->h_hdr, b->P.hdr, sizeof(nb::StepHdr), hipMemcpyDeviceToHost, b->st));
     B_HIP(b, hipStreamSynchronize(b->st));
+    if (b->h_hdr->overflow)
+        return bfail(b, NB_ERR_STATE, "partial-sum buffer overflow (%lld slots needed)",
+                     (long long)b->h_hdr->pslots);
     return NB_OK;
+}
+
+void b_outputs(nb_batch *b, int64_t *h_n_act, int64_t *h_tick_next, int32_t *h_job_err)
+{
+    for (int k = 0; k < b->p.max_jobs; ++k) {
+        const bool live = b->alive[k];
+        if (h_n_act) h_n_act[k] = live ? b->h_nact()[k] : 0;
+        if (h_tick_next) h_tick_next[k] = live ? b->h_tnext()[k] : 0;
+        if (h_job_err) h_job_err[k] = live ? b->h_err()[k] : 0;
+    }
 }
 
 }  // namespace
@@ -640,9 +1209,8 @@ nb_status nb_batch_workspace_bytes(const nb_batch_params *p, size_t *h_bytes)
     if (!h_bytes || b_check_params(p))
         return NB_ERR_ARG;
     Pool P{};
-    int32_t *dj;
-    int64_t ic, gc;
-    *h_bytes = b_layout(p, &P, &dj, &ic, &gc, nullptr);
+    int32_t *dj, *d1;
+    *h_bytes = b_layout(p, &P, &dj, &d1, nullptr);
     return NB_OK;
 }
 
@@ -654,9 +1222,8 @@ nb_status nb_batch_create(const nb_batch_params *p, void *d_workspace, size_t by
     if (b_check_params(p) || !d_workspace || ((uintptr_t)d_workspace & 255))
         return NB_ERR_ARG;
     Pool P{};
-    int32_t *dj;
-    int64_t ic, gc;
-    if (bytes < b_layout(p, &P, &dj, &ic, &gc, nullptr))
+    int32_t *dj, *d1;
+    if (bytes < b_layout(p, &P, &dj, &d1, nullptr))
         return NB_ERR_SPACE;
     nb_batch *b = new (std::nothrow) nb_batch();
     if (!b)
@@ -665,30 +1232,52 @@ nb_status nb_batch_create(const nb_batch_params *p, void *d_workspace, size_t by
     b->st = (hipStream_t)p->stream;
     b->cap = p->capacity;
     b->partial_slots = b_partial_slots(p);
-    b_layout(p, &b->P, &b->d_jobs, &b->items_cap, &b->group_cap, (char *)d_workspace);
+    b->lane_recs = b_lane_recs(p);
+    b->target = b_target(p);
+    b_layout(p, &b->P, &b->d_jobs, &b->d_one, (char *)d_workspace);
     const size_t J = (size_t)p->max_jobs;
     b->off.assign(J, 0);
     b->n.assign(J, 0);
     b->tend.assign(J, 0);
     b->alive.assign(J, 0);
     b->free_ranges.push_back({0, p->capacity});
-    bool ok = hipHostMalloc((void **)&b->h_items, 16 * (size_t)b->items_cap, 0) == hipSuccess &&
-              hipHostMalloc((void **)&b->h_desc, 8 * 5 * (size_t)b->group_cap, 0) == hipSuccess &&
-              hipHostMalloc((void **)&b->h_desc2, 8 * 5 * (size_t)b->group_cap, 0) == hipSuccess &&
-              hipHostMalloc((void **)&b->h_scalar, 64, 0) == hipSuccess &&
-              hipHostMalloc((void **)&b->h_nact, 8 * J, 0) == hipSuccess &&
-              hipHostMalloc((void **)&b->h_tnext, 8 * J, 0) == hipSuccess &&
-              hipHostMalloc((void **)&b->h_err, 4 * J, 0) == hipSuccess &&
-              hipHostMalloc((void **)&b->h_jobs, 4 * J, 0) == hipSuccess &&
-              hipHostMalloc((void **)&b->h_status, sizeof(nb::Status), 0) == hipSuccess &&
-              hipEventCreateWithFlags(&b->staged, hipEventDisableTiming) == hipSuccess;
-    b->has_event = ok;
+    b->jobs_dirty = true;
+    // persistent evaluation: as many waves as can be resident on the device
+    int dev = 0, cus = 0, per[nb::kClasses] = {0, 0, 0}, fin = 0;
+    const bool sp = p->precision == NB_SPLIT;
+    bool ok = hipGetDevice(&dev) == hipSuccess &&
+              hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+              hipOccupancyMaxActiveBlocksPerMultiprocessor(&fin, nb::k_bfinish, 256, 0) == hipSuccess;
+    if (sp)
+        ok = ok &&
+             hipOccupancyMaxActiveBlocksPerMultiprocessor(&per[nb::kClassTile],
+                                                          nb::k_beval_split<nb::kClassTile>, 64, 0) == hipSuccess &&
+             hipOccupancyMaxActiveBlocksPerMultiprocessor(&per[nb::kClassDirect],
+                                                          nb::k_beval_split<nb::kClassDirect>, 64, 0) == hipSuccess;
+    else
+        ok = ok &&
+             hipOccupancyMaxActiveBlocksPerMultiprocessor(&per[nb::kClassTile],
+                                                          nb::k_beval_f64<nb::kClassTile>, 64, 0) == hipSuccess &&
+             hipOccupancyMaxActiveBlocksPerMultiprocessor(&per[nb::kClassWide],
+                                                          nb::k_beval_f64<nb::kClassWide>, 64, 0) == hipSuccess &&
+             hipOccupancyMaxActiveBlocksPerMultiprocessor(&per[nb::kClassDirect],
+                                                          nb::k_beval_f64<nb::kClassDirect>, 64, 0) == hipSuccess;
+    for (int k = 0; k < nb::kClasses; ++k)
+        b->eval_grid[k] = std::max(1, cus * std::max(1, per[k]));
+    b->finish_grid = std::max(1, cus * std::max(1, fin));
+    ok = ok && hipHostMalloc((void **)&b->h_scalar, 64, 0) == hipSuccess &&
+         hipHostMalloc((void **)&b->h_jobblk, 20 * J, 0) == hipSuccess &&
+         hipHostMalloc((void **)&b->h_hdr, sizeof(nb::StepHdr), 0) == hipSuccess &&
+         hipHostMalloc((void **)&b->h_jobs, 4 * J, 0) == hipSuccess &&
+         hipHostMalloc((void **)&b->h_status, sizeof(nb::Status), 0) == hipSuccess;
     if (ok) {
-        ok = nb::launch_fill_i32(b->P.body_job, -1, (size_t)b->cap, b->st) == hipSuccess &&
+        hipLaunchKernelGGL(nb::k_hdr_reset, dim3(1), dim3(64), 0, b->st, b->P);
+        ok = hipGetLastError() == hipSuccess &&
+             nb::launch_fill_i32(b->P.body_job, -1, (size_t)b->cap, b->st) == hipSuccess &&
              nb::launch_fill_i32(b->P.j_err, 0, J, b->st) == hipSuccess &&
              nb::launch_fill_i64(b->P.j_nact, 0, J, b->st) == hipSuccess &&
              nb::launch_fill_i32((int32_t *)b->P.status, 0, sizeof(nb::Status) / 4, b->st) == hipSuccess &&
-             hipStreamSynchronize(b->st) == hipSuccess;
+             b_fetch(b) == NB_OK;  // the host copies start current
     }
     if (!ok) {
         nb_batch_destroy(b);
@@ -703,13 +1292,10 @@ void nb_batch_destroy(nb_batch *b)
     if (!b)
         return;
     (void)hipStreamSynchronize(b->st);
-    for (void *q : {(void *)b->h_items, (void *)b->h_desc, (void *)b->h_desc2, (void *)b->h_scalar,
-                    (void *)b->h_nact, (void *)b->h_tnext,
-                    (void *)b->h_err, (void *)b->h_jobs, (void *)b->h_status})
+    for (void *q : {(void *)b->h_scalar, (void *)b->h_jobblk, (void *)b->h_hdr, (void *)b->h_jobs,
+                    (void *)b->h_status})
         if (q)
             (void)hipHostFree(q);
-    if (b->has_event)
-        (void)hipEventDestroy(b->staged);
     delete b;
 }
 
@@ -737,56 +1323,43 @@ nb_status nb_batch_add(nb_batch *b, int64_t n, const nb_state *src, int64_t tick
             break;
     if (r == b->free_ranges.size())
         return bfail(b, NB_ERR_SPACE, "no free range of %lld bodies", (long long)n);
-    {
-        const int64_t S = (n + b_jchunk(&b->p) - 1) / b_jchunk(&b->p);
-        if ((n + nb::kItemTile - 1) / nb::kItemTile * S > b->items_cap || S * n > b->partial_slots)
-            return bfail(b, NB_ERR_SPACE, "a job of %lld bodies exceeds the work-item or partial-sum "
-                                          "capacity", (long long)n);
-    }
     const int64_t off = b->free_ranges[r].first;
     const bool synced = !src->tick;
-    // load the state
+    b->jobs_dirty = true;
+    // load the state; the pinned scalars are free (every call ends with a wait)
+    b->h_scalar[0] = tick_end;
+    reinterpret_cast<int32_t *>(b->h_scalar + 1)[0] = job;
     hipLaunchKernelGGL(nb::k_bload, dim3(nb::nblk(n, 256)), dim3(256), 0, b->st, b->P, b->cap, off, n,
                        src->m, src->x, src->v, src->a, src->j, src->s, src->c, src->a4n, src->a5n,
                        src->tick, src->level, tick0);
     hipLaunchKernelGGL(nb::k_bjob_init, dim3(nb::nblk(n, 256)), dim3(256), 0, b->st, b->P, job, off, n,
                        tick0);
     B_HIP(b, hipGetLastError());
-    B_HIP(b, hipStreamSynchronize(b->st));  // the pinned scalar may still be in use
-    b->h_scalar[0] = tick_end;
     B_HIP(b, hipMemcpyAsync(b->P.j_tend + job, b->h_scalar, 8, hipMemcpyHostToDevice, b->st));
+    B_HIP(b, hipMemcpyAsync(b->d_one, b->h_scalar + 1, 4, hipMemcpyHostToDevice, b->st));
     b->off[job] = off;
     b->n[job] = n;
     b->tend[job] = tick_end;
+    nb_status s = NB_OK;
     if (synced) {
-        // Hermite start-up of this job alone: two evaluations of every body, then levels
+        // Hermite start-up of this job alone: every body evaluated twice (the second
+        // time with the first pass's accelerations in the records), then levels
         const bool split = b->p.precision == NB_SPLIT;
-        const double ts = ldexp(1.0, b->p.dt_min_log2);
-        std::vector<int> g{job};
-        b->h_nact[job] = n;
         hipLaunchKernelGGL(nb::k_bpredict_range, dim3(nb::nblk(n, 256)), dim3(256), 0, b->st, b->P, b->cap,
-                           off, n, tick0, ts, (int)split);
-        nb_status s = b_evaluate(b, g);
-        if (!s) {
-            hipLaunchKernelGGL(nb::k_bacc_to_jrec, dim3(nb::nblk(n, 256)), dim3(256), 0, b->st, b->P, off,
-                               n, (int)split);
-            s = b_evaluate(b, g);
-        }
-        if (!s) {
-            hipLaunchKernelGGL(nb::k_bstart_store, dim3(nb::nblk(n, 256)), dim3(256), 0, b->st, b->P,
-                               b->cap, off, n);
-            s = hipGetLastError() == hipSuccess ? b_correct_levels(b, g, 1)
-                                                : bfail(b, NB_ERR_DEVICE, "start-up launch failed");
-        }
-        if (s) {
-            // leave the range and the job slot unclaimed, so no later step touches them
-            hipLaunchKernelGGL(nb::k_bfree, dim3(nb::nblk(n, 256)), dim3(256), 0, b->st, b->P, off, n);
-            (void)nb::launch_fill_i64(b->P.j_nact + job, 0, 1, b->st);
-            (void)hipStreamSynchronize(b->st);
-            return s;
-        }
+                           off, n, tick0, ldexp(1.0, b->p.dt_min_log2), (int)split);
+        s = b_eval_finish(b, b->d_one, 1, nb::kStartA, 0);
+        if (!s)
+            s = b_eval_finish(b, b->d_one, 1, nb::kStartB, 0);
     }
-    B_HIP(b, hipStreamSynchronize(b->st));
+    if (!s)
+        s = b_fetch(b);
+    if (s) {
+        // leave the range and the job slot unclaimed, so no later step touches them
+        hipLaunchKernelGGL(nb::k_bfree, dim3(nb::nblk(n, 256)), dim3(256), 0, b->st, b->P, off, n);
+        (void)nb::launch_fill_i64(b->P.j_nact + job, 0, 1, b->st);
+        (void)hipStreamSynchronize(b->st);
+        return s;
+    }
     // commit the reservation
     b->free_ranges[r].first += n;
     b->free_ranges[r].second -= n;
@@ -804,12 +1377,11 @@ nb_status nb_batch_remove(nb_batch *b, int32_t job)
     b->msg[0] = 0;
     if (job < 0 || job >= b->p.max_jobs || !b->alive[job])
         return bfail(b, NB_ERR_ARG, "job %d is not in the batch", job);
+    b->jobs_dirty = true;
     hipLaunchKernelGGL(nb::k_bfree, dim3(nb::nblk(b->n[job], 256)), dim3(256), 0, b->st, b->P, b->off[job],
                        b->n[job]);
+    B_HIP(b, nb::launch_fill_i64(b->P.j_nact + job, 0, 1, b->st));
     B_HIP(b, hipGetLastError());
-    B_HIP(b, hipStreamSynchronize(b->st));
-    b->h_scalar[1] = 0;
-    B_HIP(b, hipMemcpyAsync(b->P.j_nact + job, b->h_scalar + 1, 8, hipMemcpyHostToDevice, b->st));
     B_HIP(b, hipStreamSynchronize(b->st));
     // return the range and merge neighbours
     b->free_ranges.push_back({b->off[job], b->n[job]});
@@ -833,54 +1405,36 @@ nb_status nb_batch_step(nb_batch *b, int64_t *h_n_act, int64_t *h_tick_next, int
     if (!b)
         return NB_ERR_ARG;
     b->msg[0] = 0;
-    const int L = b->p.dt_max_log2 - b->p.dt_min_log2;
-    const bool split = b->p.precision == NB_SPLIT;
-    // jobs in the batch and not failed
-    int nj = 0;
-    for (int k = 0; k < b->p.max_jobs; ++k)
-        if (b->alive[k])
-            b->h_jobs[nj++] = k;
-    int64_t inter = 0;
-    if (nj > 0) {
-        B_HIP(b, hipMemcpyAsync(b->d_jobs, b->h_jobs, 4 * (size_t)nj, hipMemcpyHostToDevice, b->st));
-        hipLaunchKernelGGL(nb::k_bact, dim3(nj), dim3(nb::kBS), 0, b->st, b->P, (const int32_t *)b->d_jobs, L);
-        B_HIP(b, hipGetLastError());
-        nb_status s = b_fetch_jobs(b);
-        if (s) return s;
-        std::vector<int> group;
-        for (int k = 0; k < nj; ++k) {
-            const int job = b->h_jobs[k];
-            if (b->h_err[job]) {
-                b->h_nact[job] = 0;  // a failed job is not stepped again
-                continue;
-            }
-            if (b->h_nact[job] > 0) {
-                group.push_back(job);
-                inter += b->h_nact[job] * b->n[job];
-            }
-        }
-        if (!group.empty()) {
-            // failed jobs must not be predicted either
-            B_HIP(b, hipMemcpyAsync(b->P.j_nact, b->h_nact, 8 * (size_t)b->p.max_jobs,
-                                    hipMemcpyHostToDevice, b->st));
-            hipLaunchKernelGGL(nb::k_bpredict, dim3(nb::nblk(b->cap, 256)), dim3(256), 0, b->st, b->P, b->cap,
-                               ldexp(1.0, b->p.dt_min_log2), (int)split);
-            B_HIP(b, hipGetLastError());
-            if ((s = b_evaluate(b, group))) return s;
-            if ((s = b_correct_levels(b, group, 0))) return s;
-            B_HIP(b, hipMemcpyAsync(b->h_err, b->P.j_err, 4 * (size_t)b->p.max_jobs, hipMemcpyDeviceToHost,
-                                    b->st));
-            B_HIP(b, hipStreamSynchronize(b->st));
-        }
-    }
-    for (int k = 0; k < b->p.max_jobs; ++k) {
-        const bool live = b->alive[k];
-        if (h_n_act) h_n_act[k] = live ? b->h_nact[k] : 0;
-        if (h_tick_next) h_tick_next[k] = live ? b->h_tnext[k] : 0;
-        if (h_job_err) h_job_err[k] = live ? b->h_err[k] : 0;
-    }
+    nb_status s;
+    const int64_t before = b->h_hdr->inter;  // host copy is current: every call ends with a fetch
+    if ((s = b_enqueue_step(b)) || (s = b_fetch(b)))
+        return s;
+    b_outputs(b, h_n_act, h_tick_next, h_job_err);
     if (h_interactions)
-        *h_interactions = inter;
+        *h_interactions = b->h_hdr->inter - before;
+    return NB_OK;
+}
+
+nb_status nb_batch_run(nb_batch *b, int32_t steps, int64_t *h_n_act, int64_t *h_tick_next,
+                       int32_t *h_job_err, int64_t *h_interactions, int64_t *h_steps)
+{
+    if (!b)
+        return NB_ERR_ARG;
+    b->msg[0] = 0;
+    if (steps < 1)
+        return bfail(b, NB_ERR_ARG, "steps must be >= 1");
+    nb_status s;
+    const int64_t inter0 = b->h_hdr->inter, steps0 = b->h_hdr->steps;
+    for (int k = 0; k < steps; ++k)
+        if ((s = b_enqueue_step(b)))
+            return s;
+    if ((s = b_fetch(b)))
+        return s;
+    b_outputs(b, h_n_act, h_tick_next, h_job_err);
+    if (h_interactions)
+        *h_interactions = b->h_hdr->inter - inter0;
+    if (h_steps)
+        *h_steps = b->h_hdr->steps - steps0;
     return NB_OK;
 }
 
@@ -908,6 +1462,7 @@ nb_status nb_batch_energy(nb_batch *b, int32_t job, int64_t tick, double *h_ekin
     if (job < 0 || job >= b->p.max_jobs || !b->alive[job])
         return bfail(b, NB_ERR_ARG, "job %d is not in the batch", job);
     const int64_t n = b->n[job], off = b->off[job];
+    // predicting into the records is harmless: every step predicts its jobs again
     hipLaunchKernelGGL(nb::k_bpredict_range, dim3(nb::nblk(n, 256)), dim3(256), 0, b->st, b->P, b->cap, off,
                        n, tick, ldexp(1.0, b->p.dt_min_log2), 0);
     B_HIP(b, hipGetLastError());

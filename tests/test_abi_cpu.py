@@ -87,7 +87,7 @@ def test_binding_fails_loudly_without_gpu():
 
 def _bparams(**kw):
     p = dict(capacity=4096, max_jobs=16, precision=0, eps=1e-4, eta=0.45, eta_init=0.01,
-             dt_max_log2=-3, dt_min_log2=-40, jchunk=0, reserved=0, partial_slots=0, stream=None)
+             dt_max_log2=-3, dt_min_log2=-40, jchunk=0, items_per_job=0, partial_slots=0, stream=None)
     p.update(kw)
     return _abi.BatchParams(**p)
 
@@ -96,17 +96,22 @@ def test_batch_workspace_bytes_and_argument_checks(lib):
     out = ctypes.c_size_t(0)
     assert lib.nb_batch_workspace_bytes(ctypes.byref(_bparams()), ctypes.byref(out)) == 0
     fp64 = out.value
-    # pool state + j-records + evaluation block + default partial buffer (2^22 slots)
-    assert fp64 >= 4096 * (8 * 19 + 12 + 80 + 80) + 80 * (1 << 22)
+    # pool state + j-records + the partial-sum bound 2 capacity + 128 (2048 + 1) max_jobs
+    bound = 2 * 4096 + 128 * 2049 * 16
+    assert fp64 >= 4096 * (8 * 19 + 12 + 80) + 80 * bound
     assert lib.nb_batch_workspace_bytes(ctypes.byref(_bparams(precision=1)), ctypes.byref(out)) == 0
     assert out.value >= fp64 + 64 * 4096
-    assert lib.nb_batch_workspace_bytes(ctypes.byref(_bparams(partial_slots=1 << 23)),
+    assert lib.nb_batch_workspace_bytes(ctypes.byref(_bparams(partial_slots=bound + (1 << 20))),
                                         ctypes.byref(out)) == 0
-    assert out.value >= fp64 + 80 * (1 << 22)
+    assert out.value >= fp64 + 80 * (1 << 20)
+    assert lib.nb_batch_workspace_bytes(ctypes.byref(_bparams(partial_slots=16)), ctypes.byref(out)) == 0
+    assert out.value == fp64  # raised to the bound
+    assert lib.nb_batch_workspace_bytes(ctypes.byref(_bparams(items_per_job=64)), ctypes.byref(out)) == 0
+    assert out.value < fp64
     bad = [dict(capacity=0), dict(capacity=(1 << 30) + 1), dict(max_jobs=0),
-           dict(max_jobs=(1 << 20) + 1), dict(eps=-1.0), dict(eta=float("inf")),
+           dict(max_jobs=(1 << 16) + 1), dict(eps=-1.0), dict(eta=float("inf")),
            dict(dt_min_log2=-70), dict(precision=3), dict(jchunk=100), dict(jchunk=-64),
-           dict(reserved=2), dict(partial_slots=-5)]
+           dict(items_per_job=-1), dict(items_per_job=(1 << 14) + 1), dict(partial_slots=-5)]
     for kw in bad:
         assert lib.nb_batch_workspace_bytes(ctypes.byref(_bparams(**kw)), ctypes.byref(out)) == 1, kw
     b = ctypes.c_void_p(0)
@@ -118,6 +123,7 @@ def test_batch_workspace_bytes_and_argument_checks(lib):
     lib.nb_batch_destroy(None)
     assert lib.nb_batch_last_error(None) == b"null batch"
     assert lib.nb_batch_step(None, None, None, None, None) == 1
+    assert lib.nb_batch_run(None, 1, None, None, None, None, None) == 1
     assert lib.nb_batch_remove(None, 0) == 1
     assert lib.nb_batch_info(None, 0, None, None) == 1
 

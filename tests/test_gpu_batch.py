@@ -7,8 +7,8 @@ uneven size advanced together, each with its own block steps.
     end-to-end test);
   * a job's results are bitwise the same alone and in any mix of jobs, at any pool
     offset, in both precisions;
-  * admission (NB_ERR_SPACE when the pool, the job table or the work buffers have no
-    room), removal and reuse of freed ranges;
+  * admission (NB_ERR_SPACE when the pool or the job table has no room), removal
+    and reuse of freed ranges;
   * resume from a checkpoint taken with nb_batch_get is bitwise exact;
   * a failing job is flagged in its own error word and the others are unaffected.
 """
@@ -162,12 +162,13 @@ def test_batch_admission_remove_and_reuse(nb):
     # t_end is not a multiple of every step: each body stopped at its last time
     # not beyond t_end, and its next time is beyond it
     assert np.all(tick <= t_end) and np.all(tick + (np.int64(1) << (L - level)) > t_end)
-    # a job whose single evaluation cannot fit the partial-sum buffer is refused
+    # a partial-sum buffer below the bound every step fits is raised to it: any job
+    # that fits the pool is admitted
     small = make_batch(nb, 4096, 2, jchunk=64, partial_slots=1000)
     big = cluster(1024, 3)
-    assert small.add(big.m, big.x, big.v, t_end) is None
+    assert small.add(big.m, big.x, big.v, t_end) == 0
     with pytest.raises(nb.NBodyError):
-        small.get(0)
+        small.get(1)
 
 
 # ------------------------------------------------------------ checkpointing ------
