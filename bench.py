@@ -41,10 +41,20 @@ DT_MAX, DT_MIN = -3, -40
 SWEEP = (1, 64, 1024, 8192, 65536)
 METRIC = "pairwise interactions/s (acc+jerk+snap) and % of FP64/FP32 vector peak; p99"
 PEAK_FP32_TFLOPS = 157.3           # packed FP32; unpacked FP32 issues at the FP64 rate
-KERNEL_SRC = os.path.join(ROOT, "paper_1812_00367_amd", "csrc", "nbody_kernels.hip")
+# sources of the evaluation kernel; the traffic figure below is valid only for them
+KERNEL_SRCS = [os.path.join(ROOT, "paper_1812_00367_amd", "csrc", f)
+               for f in ("nbody_kernels.hip", "nb_device.h", "nb_internal.h")]
 # HBM bytes per full-N FP64 evaluation launch from the FETCH_SIZE / WRITE_SIZE runs in
-# profiles/eval_fp64_plummer65536.md, valid only for the kernel source they were taken on.
-TRAFFIC = {"949a00bf00eba2e5": {"fp64": 2.00 * 21970 * 1024 + 81920 * 1024}}
+# profiles/eval_fp64_plummer65536.md, keyed by the sha256 prefix of those sources.
+TRAFFIC = {"5ccedd78fc58d3eb": {"fp64": 2.00 * 22047 * 1024 + 81920 * 1024}}
+
+
+def kernel_sources_hash():
+    h = hashlib.sha256()
+    for path in KERNEL_SRCS:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def parse():
@@ -186,8 +196,7 @@ def main():
     achieved = FLOP_PER_INTERACTION * n * n / eval_avg_s / 1e12
     peak = PEAK_FP64_TFLOPS if prec == nb.NB_FP64 else PEAK_FP32_TFLOPS
     value = inter / elapsed
-    with open(KERNEL_SRC, "rb") as f:
-        src_hash = hashlib.sha256(f.read()).hexdigest()[:16]
+    src_hash = kernel_sources_hash()
     traffic = TRAFFIC.get(src_hash, {}).get(args.precision) if n == N_BODIES else None
 
     result = {
