@@ -69,10 +69,16 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--eval-only", type=int, default=0,
                     help="time only K nb_evaluate calls of the full active set (for profiling)")
-    ap.add_argument("--config", choices=("c2", "c3", "c4"), default="c2",
+    ap.add_argument("--config", choices=("c2", "c3", "c4", "c5"), default="c2",
                     help="c2: N=65536 block steps (the headline line); c3: N=2^20 Kroupa-mass "
                          "sphere, one full evaluation + 16 block steps on both precisions; "
-                         "c4: ensemble of 512 clusters integrated together to t=0.25")
+                         "c4: ensemble of 512 clusters integrated together to t=0.25; "
+                         "c5: continuous-batching server under Poisson arrivals (rate sweep)")
+    ap.add_argument("--rates", default="0.5,1,2,3", help="c5: arrival rates (requests/s)")
+    ap.add_argument("--requests", type=int, default=24, help="c5: requests per rate")
+    ap.add_argument("--budget-gib", type=float, default=32.0, help="c5: HBM budget of the pool")
+    ap.add_argument("--slots", type=int, default=64, help="c5: job-table size")
+    ap.add_argument("--serve-t-end", type=float, default=1.0, help="c5: end time of every job")
     ap.add_argument("--clusters", type=int, default=512, help="c4: number of clusters")
     ap.add_argument("--t-end", type=float, default=0.25, help="c4: end time (multiple of 2^-3)")
     ap.add_argument("--jchunk", type=int, default=0, help="c4: j-chunk per work item (0 = default)")
@@ -102,6 +108,11 @@ def main():
         sys.exit(1)
     if args.config == "c3":
         print(json.dumps(large_workload()), flush=True)
+        return
+    if args.config == "c5":
+        print(json.dumps(serving_workload([float(r) for r in args.rates.split(",")], args.requests,
+                                          args.budget_gib, args.slots, args.serve_t_end,
+                                          args.precision, args.steps_per_call)), flush=True)
         return
     if args.config == "c4":
         print(json.dumps(ensemble_workload(args.clusters, args.t_end, args.jchunk,
@@ -418,6 +429,48 @@ def ensemble_workload(count=512, t_end=0.25, jchunk=0, precisions=("fp64", "spli
                                       "max": float(de.max())}}
         print(f"[c4 {name}] {steps} batch steps, {inter:.3e} interactions in {wall:.1f} s "
               f"= {rate:.3e}/s", file=sys.stderr, flush=True)
+        b.close()
+        del b
+        torch.cuda.empty_cache()
+    return res
+
+
+def serving_workload(rates, count=24, budget_gib=32.0, slots=64, t_end=1.0, precision="fp64",
+                     steps_per_call=8, seed=5):
+    """Continuous-batching serving: for each arrival rate, `count` seeded requests
+    (90 % Plummer clusters with N log-uniform in [1024, 65536], 10 % parabolic pairs
+    of two N/2 spheres 10 apart), each integrated to t_end, arrive as a Poisson
+    stream; the server keeps admitted jobs resident in a pool sized from an HBM
+    budget and advances them together. Reports p50/p99 latency (arrival to result,
+    queueing and start-up included) and aggregate interactions/s."""
+    import torch
+
+    import nbody_inputs as ni
+    import paper_1812_00367_amd as nb
+    from paper_1812_00367_amd.serve import Request, Server, capacity_for_budget
+    dev = torch.device("cuda", 0)
+    prec = nb.NB_SPLIT if precision == "split" else nb.NB_FP64
+    tick_end = int(round(t_end * 2.0 ** -DT_MIN))
+    cap = capacity_for_budget(int(budget_gib * (1 << 30)), slots, prec)
+    res = {"workload": f"serving: Poisson arrivals, 90% plummer N log-uniform [1024, 65536], "
+                       f"10% parabolic pairs, to t={t_end}",
+           "budget_gib": budget_gib, "pool_bodies": cap, "slots": slots, "precision": precision,
+           "steps_per_call": steps_per_call, "rates": []}
+    for k, rate in enumerate(rates):
+        stream = ni.serving_requests(count, rate, seed + k)
+        reqs = [Request(rid=i, arrival=q["arrival"], m=q["ic"].m, x=q["ic"].x, v=q["ic"].v,
+                        tick_end=tick_end, kind=q["kind"]) for i, q in enumerate(stream)]
+        b = nb.Batch(cap, slots, eps=EPS, dt_max_log2=DT_MAX, dt_min_log2=DT_MIN, precision=prec,
+                     device=dev)
+        t0 = time.perf_counter()
+        summ = Server(b, steps_per_call=steps_per_call).run(
+            reqs, log=lambda msg: print(f"[c5 rate {rate}] {msg}", file=sys.stderr, flush=True))
+        summ["rate_per_s"] = rate
+        summ["mean_n"] = sum(r.n for r in reqs) / len(reqs)
+        summ["wall_s"] = time.perf_counter() - t0
+        res["rates"].append(summ)
+        print(f"[c5] rate {rate}/s: p50 {summ['latency_p50_s']:.2f} s, p99 {summ['latency_p99_s']:.2f} s, "
+              f"{summ['interactions_per_s']:.3e} interactions/s", file=sys.stderr, flush=True)
         b.close()
         del b
         torch.cuda.empty_cache()

@@ -213,3 +213,24 @@ def block_state(n: int, seed: int, L: int, max_level: int = 10, span: int = 64):
     mult = g.integers(0, span, n).astype(np.int64)
     tick = mult * (np.int64(1) << (L - level.astype(np.int64)))
     return tick, level
+
+
+def serving_requests(count: int, rate: float, seed: int, lo: int = 1024, hi: int = 65536,
+                     pair_fraction: float = 0.1, separation: float = 10.0):
+    """A seeded stream of integration requests: Poisson arrivals at `rate` per second
+    (exponential gaps, the first at 0) of single Plummer clusters with N log-uniform in
+    [lo, hi], a `pair_fraction` of them replaced by two equal Plummer spheres of N/2
+    each on a parabolic orbit `separation` apart. Returns a list of dicts
+    {arrival, kind, n, ic}."""
+    g = rng(seed)
+    t = 0.0
+    out = []
+    for k in range(count):
+        if k:
+            t += float(g.exponential(1.0 / rate))
+        pair = bool(g.random() < pair_fraction)
+        n = log_uniform_n(g, lo, hi, even=pair)
+        s = int(g.integers(0, 2**31 - 1))
+        ic = parabolic_pair(n, s, separation=separation) if pair else plummer(n, s)
+        out.append({"arrival": t, "kind": "pair" if pair else "cluster", "n": n, "ic": ic})
+    return out
