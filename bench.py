@@ -85,6 +85,9 @@ def parse():
     ap.add_argument("--precisions", default="fp64,split", help="c4: precisions to run")
     ap.add_argument("--steps-per-call", type=int, default=32,
                     help="c4: batch steps enqueued per call without a host wait")
+    ap.add_argument("--energy-seconds", type=float, default=3.0,
+                    help="length of the untimed run of the same step under the GPU energy "
+                         "counter (0 = skip)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run one device-to-device copy of this many MiB (a known-size "
                          "kernel against which HBM byte counters are scaled)")
@@ -235,11 +238,44 @@ def main():
         "energy": {"ekin": ek, "epot": ep, "ms": t_energy * 1e3},
     }
 
+    if args.energy_seconds > 0:
+        result["energy_per_interaction"] = energy_leg(restore, one_step, n, args.energy_seconds)
     if not args.no_sweep:
         result["sweep"] = sweep(sim, ic, n, stream, dev, peak)
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(ic, n, args.cpu_seconds)
     print(json.dumps(result), flush=True)
+
+
+def energy_leg(restore, one_step, n, seconds):
+    """GPU energy per interaction: the headline step repeated for about `seconds`
+    under the device's accumulated-energy counter (sampled socket power beside it).
+    Separate from the timed region; reported as nJ per interaction."""
+    import torch
+
+    from paper_1812_00367_amd.power import EnergyMeter
+    meter = EnergyMeter(0)
+    if not meter.available:
+        return {"nJ": None, "reason": meter.reason}
+    # size the run from one timed step
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    restore()
+    one_step()
+    torch.cuda.synchronize()
+    per = time.perf_counter() - t
+    steps = max(1, int(seconds / max(per, 1e-4)))
+    meter.start()
+    inter = 0
+    for _ in range(steps):
+        restore()
+        inter += one_step() * n
+    torch.cuda.synchronize()
+    rec = meter.stop()
+    rec.update({"steps": steps, "interactions": inter,
+                "nJ": rec["joules"] / inter * 1e9 if rec.get("joules") else None,
+                "interactions_per_joule": inter / rec["joules"] if rec.get("joules") else None})
+    return rec
 
 
 def sweep(sim, ic, n, stream, dev, peak):

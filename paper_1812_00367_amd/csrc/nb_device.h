@@ -53,6 +53,18 @@ __device__ __forceinline__ int wave_sum_i32(int v)
     return v;
 }
 
+// Whether any lane of the wave holds an own body with index in [j0, j0 + len): the
+// self pair is masked only on such tiles (wave-uniform decision).
+template <typename B, int IPL>
+__device__ __forceinline__ bool wave_has_self(const B (&b)[IPL], int j0, int len)
+{
+    bool mine = false;
+#pragma unroll
+    for (int q = 0; q < IPL; ++q)
+        mine |= (unsigned)(b[q].self - j0) < (unsigned)len;
+    return __ballot(mine) != 0;
+}
+
 // 1/sqrt(x) to about one ulp: the hardware estimate v_rsq_f64 (relative error
 // below 2^-24 measured on gfx950) followed by one third-order correction
 // y (1 + e/2 + 3 e^2 / 8) with e = 1 - x y^2, whose truncation error (5/16) e^3 is
@@ -216,7 +228,7 @@ __device__ __forceinline__ void tiles_f64(const double *__restrict__ jrec, int j
             gload(t + 1);
         const int j0 = jbeg + t * TILE;
         const double2 *L = lds[buf];
-        if (hi < j0 || lo >= j0 + TILE) {
+        if ((hi < j0 || lo >= j0 + TILE) || !wave_has_self(b, j0, TILE)) {
             // the next record's LDS reads are issued before this record's arithmetic
             double2 p0 = L[0], p1 = L[1], p2 = L[2], p3 = L[3], p4 = L[4];
 #pragma unroll 2
@@ -402,7 +414,7 @@ __device__ __forceinline__ void tiles_split(const float *__restrict__ jrec, int 
             gload(t + 1);
         const int j0 = jbeg + t * TILE;
         const float4 *L = lds[buf];
-        const bool masked = !(hi < j0 || lo >= j0 + TILE);
+        const bool masked = !(hi < j0 || lo >= j0 + TILE) && wave_has_self(b, j0, TILE);
         for (int jf = 0; jf < TILE; jf += kFold) {
             if (!masked) {
 #pragma unroll 4

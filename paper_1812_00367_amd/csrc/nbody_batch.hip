@@ -480,6 +480,7 @@ __device__ __forceinline__ Rec64 load_rec64(const double2 *__restrict__ src, int
 __device__ __forceinline__ void sweep_direct_f64(const double2 *__restrict__ src, int jbeg, int jend,
                                                  int W, int w, I64 &b, int lo, int hi, double eps2)
 {
+    const I64(&one)[1] = reinterpret_cast<const I64(&)[1]>(b);
     const int rounds = (jend - jbeg + W - 1) / W;
     auto idx = [&](int k) { return jbeg + k * W + w; };
     auto at = [&](int k) { const int j = idx(k); return j < jend ? j : jbeg; };
@@ -488,7 +489,7 @@ __device__ __forceinline__ void sweep_direct_f64(const double2 *__restrict__ src
     for (int k = 0; k < rounds; ++k) {
         const Rec64 f = load_rec64(src, at(k + 2 < rounds ? k + 2 : k));
         const int r0 = jbeg + k * W;
-        if (r0 + W <= jend && (hi < r0 || lo >= r0 + W)) {
+        if (r0 + W <= jend && ((hi < r0 || lo >= r0 + W) || !wave_has_self(one, r0, W))) {
             interact_f64<false>(b, c.p0, c.p1, c.p2, c.p3, c.p4, eps2, 0);
         } else {
             const int j = idx(k);
@@ -655,6 +656,7 @@ __device__ __forceinline__ void fold32(I32 &b)
 __device__ __forceinline__ void sweep_direct_split(const float4 *__restrict__ src, int jbeg, int jend,
                                                    int W, int w, I32 &b, int lo, int hi, float eps2)
 {
+    const I32(&one)[1] = reinterpret_cast<const I32(&)[1]>(b);
     const int rounds = (jend - jbeg + W - 1) / W;
     auto idx = [&](int k) { return jbeg + k * W + w; };
     auto at = [&](int k) { const int j = idx(k); return j < jend ? j : jbeg; };
@@ -663,7 +665,7 @@ __device__ __forceinline__ void sweep_direct_split(const float4 *__restrict__ sr
     for (int k = 0; k < rounds; ++k) {
         const Rec32 f = load_rec32(src, at(k + 2 < rounds ? k + 2 : k));
         const int r0 = jbeg + k * W;
-        if (r0 + W <= jend && (hi < r0 || lo >= r0 + W)) {
+        if (r0 + W <= jend && ((hi < r0 || lo >= r0 + W) || !wave_has_self(one, r0, W))) {
             interact_f32<false>(b, c.p0, c.p1, c.p2, c.p3, eps2, 0);
         } else {
             const int j = idx(k);
@@ -681,6 +683,7 @@ __device__ __forceinline__ void sweep_lds_split(const float4 *__restrict__ src, 
                                                 int W, int lw, int w, I32 &b, int lo, int hi, float eps2,
                                                 float4 (*lds)[kItemTile * 4])
 {
+    const I32(&one)[1] = reinterpret_cast<const I32(&)[1]>(b);
     const int lane = threadIdx.x;
     const int ntiles = (jend - jbeg + kItemTile - 1) / kItemTile;
     float4 stage[kStageF];
@@ -722,7 +725,7 @@ __device__ __forceinline__ void sweep_lds_split(const float4 *__restrict__ src, 
         const int j0 = jbeg + t * kItemTile;
         const float4 *L = lds[buf] + w * 4;
         const int step = W * 4;
-        const bool masked = !(hi < j0 || lo >= j0 + kItemTile);
+        const bool masked = !(hi < j0 || lo >= j0 + kItemTile) && wave_has_self(one, j0, kItemTile);
         for (int k = 0; k < per; ++k) {
             const int e = k * step;
             if (masked)

@@ -9,6 +9,12 @@ covers active sets up to the geometric midpoint to the next tuned size.
     python -m paper_1812_00367_amd.tune [--n 65536] [--precision fp64|split]
 
 prints the table as JSON (and as a C initializer).
+
+    python -m paper_1812_00367_amd.tune --batch 128 [--precision fp64|split]
+
+tunes the batch path instead: it times an ensemble of clusters for each pair of
+(j-records per lane, work items per job) and prints the fastest pair, to be passed
+to Batch(jchunk=..., items_per_job=...) / nb_batch_params.
 """
 from __future__ import annotations
 
@@ -84,12 +90,69 @@ def tune(sim, sizes=None, seed=20, shapes=SHAPES, targets=TARGETS, log=None):
     return merged, results
 
 
+BATCH_JCHUNKS = [64, 128, 192, 256]
+BATCH_TARGETS = [512, 2048, 8192]
+
+
+def tune_batch(clusters, tick_end, precision, jchunks=BATCH_JCHUNKS, targets=BATCH_TARGETS,
+               steps_per_call=32, log=None):
+    """Time the batch path on an ensemble for every (jchunk, items_per_job) pair and
+    return (best (jchunk, items_per_job), {pair: interactions/s}). `clusters` is a
+    list of objects with m, x, v (one job each), all integrated to tick_end."""
+    import time
+
+    import torch
+
+    from .batch import Batch
+    cap = sum(len(ic.m) for ic in clusters)
+    rates = {}
+    for jc in jchunks:
+        for tg in targets:
+            b = Batch(cap, len(clusters), precision=precision, jchunk=jc, items_per_job=tg)
+            for ic in clusters:
+                if b.add(ic.m, ic.x, ic.v, tick_end) is None:
+                    raise RuntimeError("ensemble does not fit")
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            inter = 0
+            while True:
+                _, _, _, it, taken = b.run_steps(steps_per_call)
+                inter += it
+                if taken < steps_per_call:
+                    break
+            dt = time.perf_counter() - t0
+            rates[(jc, tg)] = inter / dt
+            if log:
+                log(f"jchunk={jc} items_per_job={tg}: {inter / dt:.3e} interactions/s ({dt:.2f} s)")
+            b.close()
+    best = max(rates, key=rates.get)
+    return best, rates
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--n", type=int, default=65536)
     ap.add_argument("--precision", choices=("fp64", "split"), default="fp64")
     ap.add_argument("--seed", type=int, default=2)
+    ap.add_argument("--batch", type=int, default=0,
+                    help="tune the batch path instead, on an ensemble of this many Plummer "
+                         "clusters (N log-uniform in [256, 16384], Kroupa masses) to t = 0.125")
     args = ap.parse_args()
+    if args.batch:
+        import nbody_inputs as ni
+        import paper_1812_00367_amd as nb
+        g = ni.rng(args.seed)
+        clusters = []
+        for _ in range(args.batch):
+            n = ni.log_uniform_n(g, 256, 16384)
+            s = int(g.integers(0, 2**31 - 1))
+            clusters.append(ni.plummer(n, s, masses=ni.kroupa_masses(n, s + 1)))
+        prec = nb.NB_SPLIT if args.precision == "split" else nb.NB_FP64
+        best, rates = tune_batch(clusters, 1 << 37, prec, log=lambda m: print(m, flush=True))
+        print(json.dumps({"clusters": args.batch, "precision": args.precision,
+                          "best": {"jchunk": best[0], "items_per_job": best[1]},
+                          "rates": {f"{k[0]}/{k[1]}": v for k, v in rates.items()}}), flush=True)
+        return
     import nbody_inputs as ni
     import paper_1812_00367_amd as nb
     ic = ni.plummer(args.n, args.seed)

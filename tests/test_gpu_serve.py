@@ -34,9 +34,10 @@ def test_served_jobs_equal_their_solo_runs(nb):
         n = ni.log_uniform_n(g, 128, 1500, even=pair)
         s = int(g.integers(0, 2**31 - 1))
         ic = ni.parabolic_pair(n, s) if pair else ni.plummer(n, s, masses=ni.kroupa_masses(n, s + 1))
-        reqs.append(Request(rid=k, arrival=t, m=ic.m, x=ic.x, v=ic.v, tick_end=1 << (L - 1),
+        # the first three arrive together (resident at once), the rest while they run
+        reqs.append(Request(rid=k, arrival=t, m=ic.m, x=ic.x, v=ic.v, tick_end=1 << L,
                             kind="pair" if pair else "cluster"))
-        t += 0.02
+        t += 0.0 if k < 2 else 0.002
     # a pool for about three of them at a time: later requests wait for room
     cap = 3000
     b = nb.Batch(cap, 4, eps=1e-4, dt_max_log2=DT_MAX, dt_min_log2=DT_MIN)

@@ -127,3 +127,14 @@ def test_percentile_interpolates():
     assert _percentile([1, 2, 3, 4], 50) == 2.5
     assert _percentile([5], 99) == 5
     assert _percentile([1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11], 100) == 11
+
+
+def test_energy_counter_arithmetic():
+    from paper_1812_00367_amd.power import joules_from_counter, mean_power
+    assert joules_from_counter(100, 1100, 15.3) == pytest.approx(1000 * 15.3e-6)
+    # wrap-around of a 64-bit accumulator
+    assert joules_from_counter((1 << 64) - 10, 5, 1.0) == pytest.approx(15e-6)
+    # trapezoid mean of a ramp 100 W -> 300 W over 2 s with an extra sample is 200 W
+    assert mean_power([(0.0, 100.0), (1.0, 200.0), (2.0, 300.0)]) == pytest.approx(200.0)
+    assert mean_power([(0.0, 100.0), (2.0, 300.0), (0.5, 150.0)]) == pytest.approx(200.0)
+    assert mean_power([]) is None
