@@ -8,6 +8,7 @@ nothing from it. The arithmetic lives in ``nbody_oracle.c`` (built with
 
 Parity status of each function (what pins it is in the tests under ``tests/``):
   evaluate   pinned  (finite differences, -grad phi, Newton's third law, closed forms)
+  evaluate_crackle  pinned  (third time derivative by finite differences, Newton's law)
   predict    pinned  (exact on polynomial motion of degree <= 5)
   correct    pinned  (exact on polynomial accelerations; interpolation exact)
   timesteps  block rules pinned by hand cases; the criterion's formula itself is a
@@ -66,6 +67,8 @@ def configure(lib):
     that load deliberately broken copies of it)."""
     lib.nbo_evaluate.argtypes = [_i64, _d, _d, _d, _d, _dbl, _i64, _i32p, _d, _int]
     lib.nbo_evaluate.restype = _int
+    lib.nbo_evaluate_crackle.argtypes = [_i64, _d, _d, _d, _d, _d, _dbl, _i64, _i32p, _d, _int]
+    lib.nbo_evaluate_crackle.restype = _int
     lib.nbo_predict.argtypes = [_i64, _i64p, _i64, _int, _d, _d, _d, _d, _d, _d, _d, _d, _d]
     lib.nbo_predict.restype = _int
     lib.nbo_correct.argtypes = [_i64, _i64, _i32p, _i64, _int, _d, _i64p, _d, _d, _d, _d,
@@ -127,6 +130,26 @@ def evaluate(m, xp, vp, ap, eps, idx=None, nthreads=None):
     rc = lib.nbo_evaluate(n, pm, px, pv, pa, float(eps), idx.shape[0], _p(idx, _i32p),
                           _p(out, _d), nthreads or default_threads())
     _check(rc, "evaluate")
+    return out
+
+
+def evaluate_crackle(m, xp, vp, ap, jp, eps, idx=None, nthreads=None):
+    """evaluate() plus crackle (third derivative of the acceleration) from the
+    predicted jerks jp. Returns out[13][n_act] (a, j, s, crackle, phi)."""
+    lib = _load()
+    m, pm = _f64(m)
+    n = m.shape[0]
+    xp, px = _f64(np.reshape(xp, (3, n)))
+    vp, pv = _f64(np.reshape(vp, (3, n)))
+    ap, pa = _f64(np.reshape(ap, (3, n)))
+    jp, pj = _f64(np.reshape(jp, (3, n)))
+    if idx is None:
+        idx = np.arange(n, dtype=np.int32)
+    idx = np.ascontiguousarray(idx, dtype=np.int32)
+    out = np.zeros((13, idx.shape[0]))
+    rc = lib.nbo_evaluate_crackle(n, pm, px, pv, pa, pj, float(eps), idx.shape[0], _p(idx, _i32p),
+                                  _p(out, _d), nthreads or default_threads())
+    _check(rc, "evaluate_crackle")
     return out
 
 

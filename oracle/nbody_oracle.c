@@ -121,6 +121,73 @@ int nbo_evaluate(int64_t n, const double *m, const double *xp, const double *vp,
     return ORC_OK;
 }
 
+/*
+ * The same evaluation extended by one derivative: crackle, the third time
+ * derivative of the acceleration (the term an 8th-order Hermite scheme, or an
+ * exact initial third derivative for the 6th-order one, needs; Nitadori & Makino
+ * 2008). With j = j_j - j_i the relative predicted jerk, along r' = v, v' = a,
+ * a' = j:
+ *     C = dS/dt = m_j j / R^(3/2) - 9 alpha S - 9 beta J - 3 gamma A,
+ *     gamma = (3 v.a + r.j) / R + alpha (3 beta - 4 alpha^2)
+ * (alpha' = beta - 3 alpha^2 and beta' = (3 v.a + r.j) / R - 4 alpha^3 give it).
+ * Output out[c*n_act + q], c = 0..12 = a(3) j(3) s(3) c(3) phi.
+ */
+int nbo_evaluate_crackle(int64_t n, const double *m, const double *xp, const double *vp,
+                         const double *ap, const double *jp, double eps, int64_t n_act,
+                         const int32_t *idx, double *out, int nthreads)
+{
+    if (n < 0 || n_act < 0 || n_act > n || eps < 0.0 || nthreads < 1)
+        return ORC_ERR_ARG;
+    for (int64_t q = 0; q < n_act; ++q)
+        if (idx[q] < 0 || idx[q] >= n)
+            return ORC_ERR_ARG;
+    const double eps2 = eps * eps;
+#pragma omp parallel for schedule(static) num_threads(nthreads)
+    for (int64_t q = 0; q < n_act; ++q) {
+        const int64_t i = idx[q];
+        csum acc[13];
+        memset(acc, 0, sizeof acc);
+        for (int64_t j = 0; j < n; ++j) {
+            if (j == i)
+                continue;
+            double r[3], v[3], a[3], jj[3];
+            for (int k = 0; k < 3; ++k) {
+                r[k] = xp[k * n + j] - xp[k * n + i];
+                v[k] = vp[k * n + j] - vp[k * n + i];
+                a[k] = ap[k * n + j] - ap[k * n + i];
+                jj[k] = jp[k * n + j] - jp[k * n + i];
+            }
+            const double R = r[0] * r[0] + r[1] * r[1] + r[2] * r[2] + eps2;
+            const double sqR = sqrt(R);
+            const double m3 = m[j] / (R * sqR);
+            const double va = v[0] * a[0] + v[1] * a[1] + v[2] * a[2];
+            const double rj = r[0] * jj[0] + r[1] * jj[1] + r[2] * jj[2];
+            const double alpha = (r[0] * v[0] + r[1] * v[1] + r[2] * v[2]) / R;
+            const double beta = (v[0] * v[0] + v[1] * v[1] + v[2] * v[2]
+                                 + r[0] * a[0] + r[1] * a[1] + r[2] * a[2]) / R
+                                + alpha * alpha;
+            const double gamma = (3.0 * va + rj) / R + alpha * (3.0 * beta - 4.0 * alpha * alpha);
+            double A[3], J[3], S[3], C[3];
+            for (int k = 0; k < 3; ++k) {
+                A[k] = m3 * r[k];
+                J[k] = m3 * v[k] - 3.0 * alpha * A[k];
+                S[k] = m3 * a[k] - 6.0 * alpha * J[k] - 3.0 * beta * A[k];
+                C[k] = m3 * jj[k] - 9.0 * alpha * S[k] - 9.0 * beta * J[k] - 3.0 * gamma * A[k];
+            }
+            for (int k = 0; k < 3; ++k) {
+                cs_add(&acc[k], A[k]);
+                cs_add(&acc[3 + k], J[k]);
+                cs_add(&acc[6 + k], S[k]);
+                cs_add(&acc[9 + k], C[k]);
+            }
+            cs_add(&acc[12], -(m[j] / sqR));
+        }
+        for (int c = 0; c < 13; ++c)
+            out[c * n_act + q] = cs_val(&acc[c]);
+    }
+    return ORC_OK;
+}
+
 /* ------------------------------------------------------------ predictor ---- */
 /*
  * Taylor prediction of every body to the block time t_next, h = t_next - t_i:

@@ -196,3 +196,48 @@ def test_single_body_has_no_force():
     out = oracle.evaluate(np.array([1.0]), np.zeros((3, 1)), np.zeros((3, 1)),
                           np.zeros((3, 1)), 0.0)
     assert np.array_equal(out, np.zeros((10, 1)))
+
+
+# ------------------------------------------------------------------ crackle --
+def _traj3(x, v, a, jk, t):
+    n = x.shape[1]
+    return [[mp.mpf(x[k, j]) + mp.mpf(v[k, j]) * t + mp.mpf(a[k, j]) * t * t / 2
+             + mp.mpf(jk[k, j]) * t * t * t / 6 for k in range(3)] for j in range(n)]
+
+
+@pytest.mark.parametrize("eps", [0.0, 3e-2])
+def test_crackle_is_third_time_derivative(eps):
+    """Crackle against the third time derivative of the softened acceleration
+    along the cubic trajectories x(t) = x + v t + a t^2/2 + j t^3/6 (40 digits);
+    a, j, s of the same call against the first two derivatives as well."""
+    n = 6
+    m, x, v, a = _random_system(n, 13)
+    jk = ni.rng(14).normal(0, 2.0, (3, n))
+    out = oracle.evaluate_crackle(m, x, v, a, jk, eps)
+    for i in range(n):
+        ref = [[], [], [], []]
+        for k in range(3):
+            def comp(t, k=k):
+                return _mp_acc_direct(i, m, _traj3(x, v, a, jk, t), eps)[k]
+            for d in range(4):
+                ref[d].append(mp.diff(comp, 0, d))
+        assert _rel(out[0:3, i], ref[0]) < 1e-14, ("acc", i)
+        assert _rel(out[3:6, i], ref[1]) < 1e-13, ("jerk", i)
+        assert _rel(out[6:9, i], ref[2]) < 1e-13, ("snap", i)
+        assert _rel(out[9:12, i], ref[3]) < 1e-12, ("crackle", i)
+
+
+def test_crackle_newton_third_law_and_consistency():
+    n = 40
+    m, x, v, a = _random_system(n, 15)
+    jk = ni.rng(16).normal(0, 2.0, (3, n))
+    out = oracle.evaluate_crackle(m, x, v, a, jk, 1e-3)
+    scale = np.abs(m[None, :] * out[9:12]).sum()
+    assert np.abs((m[None, :] * out[9:12]).sum(axis=1)).max() < 1e-13 * scale
+    # the a, j, s, phi rows are the plain evaluation's (same arithmetic, same order)
+    ref = oracle.evaluate(m, x, v, a, 1e-3)
+    assert np.array_equal(out[0:9], ref[0:9]) and np.array_equal(out[12], ref[9])
+    # crackle does not depend on the jerk of the body itself only through j_j - j_i:
+    # a common jerk added to every body changes nothing
+    out2 = oracle.evaluate_crackle(m, x, v, a, jk + np.array([[0.3], [-1.2], [0.7]]), 1e-3)
+    assert np.allclose(out2[9:12], out[9:12], rtol=1e-12, atol=1e-12 * np.abs(out[9:12]).max())

@@ -1,6 +1,6 @@
 """The pins are strong enough: each plausible mistake planted in a copy of the
-oracle (a dropped term, a wrong sign, coefficient or index, a transposed operand)
-makes at least one pin fail. The mutants are compiled on the CPU into a temporary
+oracle (a dropped term, a wrong sign, coefficient or index, a transposed operand;
+in every function that writes the formula out) makes at least one pin fail. The mutants are compiled on the CPU into a temporary
 directory and swapped in for the real oracle library for the duration of a check.
 """
 import ctypes
@@ -47,11 +47,19 @@ MUTANTS = [
     ("active set: max instead of min", "if (e < tn)", "if (e > tn || tn == INT64_MAX)"),
     ("energy: potential double counted", "cs_add(&ep, -0.5 * m[i] * phi[i]);",
      "cs_add(&ep, -1.0 * m[i] * phi[i]);"),
+    ("crackle: v.a weight in gamma", "(3.0 * va + rj) / R", "(2.0 * va + rj) / R"),
+    ("crackle: alpha^3 weight in gamma", "(3.0 * beta - 4.0 * alpha * alpha)",
+     "(3.0 * beta - 3.0 * alpha * alpha)"),
+    ("crackle: beta J weight", "- 9.0 * beta * J[k]", "- 6.0 * beta * J[k]"),
+    ("crackle: wrong index in relative jerk", "jj[k] = jp[k * n + j] - jp[k * n + i];",
+     "jj[k] = jp[k * n + j] - jp[k * n + j];"),
+    ("crackle: dropped r.j", "(3.0 * va + rj) / R", "(3.0 * va) / R"),
 ]
 
 PINS = [
     lambda: te.test_acceleration_is_minus_grad_potential(1e-2),
     lambda: te.test_jerk_and_snap_are_time_derivatives(3e-2),
+    lambda: te.test_crackle_is_third_time_derivative(3e-2),
     lambda: te.test_newton_third_law_and_torque(),
     lambda: te.test_two_body_closed_form(),
     lambda: tg.test_predictor_exact_on_degree5_motion(),
@@ -87,7 +95,8 @@ def test_real_oracle_passes_every_pin():
 
 @pytest.mark.parametrize("name,old,new", MUTANTS, ids=[m[0] for m in MUTANTS])
 def test_mutant_is_caught(tmp_path, source, name, old, new):
-    assert source.count(old) == 1, f"mutation site not unique: {old!r}"
+    # a formula written out in more than one function gets the mistake everywhere
+    assert source.count(old) >= 1, f"mutation site not found: {old!r}"
     mutant_src = tmp_path / "mutant.c"
     mutant_src.write_text(source.replace(old, new))
     so = tmp_path / "libmutant.so"
