@@ -83,7 +83,7 @@ def configure(lib):
     lib.nbo_energy.restype = _int
     lib.nbo_integrate.argtypes = [_i64, _d, _d, _d, _d, _d, _d, _d, _d, _d, _i64p, _i32p,
                                   _dbl, _dbl, _dbl, _int, _int, _i64, _i64, _i64p, _i64p,
-                                  _d, _int]
+                                  _d, _int, _int]
     lib.nbo_integrate.restype = _i64
     return lib
 
@@ -270,8 +270,9 @@ def energy(m, x, v, eps, nthreads=None):
 
 
 def integrate(st: State, eps, eta, eta_init, dt_max_log2, dt_min_log2, tick_end,
-              max_steps=1 << 20, nthreads=None):
+              max_steps=1 << 20, nthreads=None, start_crackle=False):
     """Block-step integration of a synchronised state to tick_end (in place).
+    start_crackle: start from the evaluated crackle instead of c = 0.
     Returns (steps, step_tick[steps], step_nact[steps], interactions)."""
     lib = _load()
     stt = np.zeros(max_steps, dtype=np.int64)
@@ -282,7 +283,8 @@ def integrate(st: State, eps, eta, eta_init, dt_max_log2, dt_min_log2, tick_end,
                               _p(st.a5n, _d), _p(st.tick, _i64p), _p(st.level, _i32p),
                               float(eps), float(eta), float(eta_init), int(dt_max_log2),
                               int(dt_min_log2), int(tick_end), max_steps, _p(stt, _i64p),
-                              _p(sna, _i64p), ctypes.byref(inter), nthreads or default_threads())
+                              _p(sna, _i64p), ctypes.byref(inter), int(bool(start_crackle)),
+                              nthreads or default_threads())
     if steps < 0:
         _check(-steps, "integrate")
     k = min(steps, max_steps)

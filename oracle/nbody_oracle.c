@@ -451,7 +451,9 @@ int nbo_energy(int64_t n, const double *m, const double *x, const double *v,
  *
  * Start: predicted state = state; pass 1 evaluates a and j (they do not depend on
  * the predicted accelerations), pass 2 evaluates s with the predicted
- * accelerations set to the pass-1 a; c = 0; initial levels from the init rule.
+ * accelerations set to the pass-1 a; c = 0, or with start_crackle a third pass
+ * that evaluates the crackle with the predicted jerks set to the pass-2 j and
+ * stores it as c; initial levels from the init rule.
  * Step: active set and t_next; predict every body to t_next; evaluate the active
  * bodies; correct them; new levels for them. Repeat until t_next > tick_end.
  *
@@ -464,7 +466,8 @@ int64_t nbo_integrate(int64_t n, const double *m, double *x, double *v, double *
                       int64_t *tick, int32_t *level, double eps, double eta,
                       double eta_init, int dt_max_log2, int dt_min_log2,
                       int64_t tick_end, int64_t max_steps, int64_t *step_tick,
-                      int64_t *step_nact, double *interactions, int nthreads)
+                      int64_t *step_nact, double *interactions, int start_crackle,
+                      int nthreads)
 {
     const int L = dt_max_log2 - dt_min_log2;
     if (n < 1 || L < 0 || L > 62 || max_steps < 0)
@@ -512,6 +515,18 @@ int64_t nbo_integrate(int64_t n, const double *m, double *x, double *v, double *
         }
     for (int64_t i = 0; i < n; ++i)
         a4n[i] = a5n[i] = 0.0;
+    if (start_crackle) {
+        double *out13 = (double *)malloc(sizeof(double) * 13 * (size_t)n);
+        if (!out13) { rc = ORC_ERR_ARG; goto done; }
+        rc = nbo_evaluate_crackle(n, m, xp, vp, ap, jk, eps, n, idx, out13, nthreads);
+        if (!rc)
+            for (int k = 0; k < 3; ++k)
+                for (int64_t i = 0; i < n; ++i)
+                    c[k * n + i] = out13[(9 + k) * n + i];
+        free(out13);
+        if (rc) goto done;
+        inter += (double)n * (double)n;
+    }
     rc = nbo_timesteps(n, n, idx, 1, tick, level, a, jk, s, c, a4n, a5n, eta, eta_init,
                        dt_max_log2, dt_min_log2);
     if (rc) goto done;

@@ -270,3 +270,41 @@ def test_block_invariants_plummer():
     assert np.all(st.tick == t_end)
     assert np.all((st.level >= 0) & (st.level <= L))
     assert inter == pytest.approx(2 * 128 * 128 + sna.sum() * 128)
+
+
+def test_crackle_start_matches_kepler_third_derivative():
+    """On the closed-form Kepler orbit (e = 0.5, at pericentre) the crackle start
+    sets c to the third time derivative of each body's acceleration, taken by
+    40-digit differentiation of the exact solution."""
+    import mpmath as mp
+    mp.mp.dps = 40
+    e = mp.mpf("0.5")
+
+    def accel2(t):
+        E = mp.findroot(lambda E: E - e * mp.sin(E) - t, t)
+        rx, ry = mp.cos(E) - e, mp.sqrt(1 - e * e) * mp.sin(E)
+        r3 = (rx * rx + ry * ry) ** mp.mpf(1.5)
+        # body 2 sits at +r/2; its acceleration from body 1 (mass 1/2) is -r / (2 |r|^3)
+        return [-rx / (2 * r3), -ry / (2 * r3)]
+
+    st = _kepler_state()
+    oracle.integrate(st, 0.0, 0.45, 0.01, -3, DT_MIN_LOG2, 0, start_crackle=True)
+    for k in range(2):
+        ref = mp.diff(lambda t: accel2(t)[k], 0, 3)
+        assert abs(st.c[k, 1] - float(ref)) <= 1e-12 * max(1.0, abs(float(ref))), (k, st.c[:, 1], ref)
+        assert st.c[k, 0] == pytest.approx(-st.c[k, 1], rel=1e-14, abs=1e-14)
+
+
+def test_crackle_start_sets_the_evaluated_crackle():
+    """With the crackle start the initial c is the crackle evaluated from the
+    start-up passes' a and j (zero steps taken)."""
+    import nbody_inputs as ni
+    ic = ni.plummer(64, 5)
+    st = oracle.State(m=ic.m, x=ic.x, v=ic.v)
+    oracle.integrate(st, 1e-3, 0.45, 0.01, -3, -40, 0, start_crackle=True)
+    # reference: the two start-up passes by hand, then the crackle evaluation
+    p1 = oracle.evaluate(ic.m, ic.x, ic.v, np.zeros((3, 64)), 1e-3)
+    p2 = oracle.evaluate(ic.m, ic.x, ic.v, p1[0:3], 1e-3)
+    ref = oracle.evaluate_crackle(ic.m, ic.x, ic.v, p1[0:3], p2[3:6], 1e-3)
+    assert np.array_equal(st.c, ref[9:12]) and np.array_equal(st.j, p2[3:6])
+    assert np.any(st.c != 0.0)
