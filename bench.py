@@ -242,9 +242,33 @@ def main():
         result["energy_per_interaction"] = energy_leg(restore, one_step, n, args.energy_seconds)
     if not args.no_sweep:
         result["sweep"] = sweep(sim, ic, n, stream, dev, peak)
+        result["crackle"] = crackle_leg(sim, n, stream)
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(ic, n, args.cpu_seconds)
     print(json.dumps(result), flush=True)
+
+
+FLOP_PER_INTERACTION_CRACKLE = 127   # the 79 above plus 48 for the crackle term
+
+
+def crackle_leg(sim, n, stream, reps=5):
+    """nb_evaluate_crackle over the full active set of the predicted state (FP64)."""
+    import torch
+    idx = torch.arange(n, dtype=torch.int32, device=sim.device)
+    out = torch.empty((13, n), dtype=torch.float64, device=sim.device)
+    sim.evaluate_crackle(idx, out)              # warm-up
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    for a, b in ev:
+        a.record(stream)
+        sim.evaluate_crackle(idx, out)
+        b.record(stream)
+    torch.cuda.synchronize()
+    ms = sorted(a.elapsed_time(b) for a, b in ev)[reps // 2]
+    rate = n * n / (ms / 1e3)
+    return {"n_act": n, "median_ms": ms, "interactions_per_s": rate,
+            "flop_per_interaction": FLOP_PER_INTERACTION_CRACKLE,
+            "tflops": rate * FLOP_PER_INTERACTION_CRACKLE / 1e12,
+            "peak_frac": rate * FLOP_PER_INTERACTION_CRACKLE / (PEAK_FP64_TFLOPS * 1e12)}
 
 
 def energy_leg(restore, one_step, n, seconds):

@@ -71,6 +71,12 @@ typedef enum {
     NB_SPLIT = 1  /* evaluation: float-float differences, FP32 algebra, FP64 sums */
 } nb_precision;
 
+/* nb_params.flags: nb_start also evaluates the exact third derivative of every
+ * body's acceleration (crackle, nb_evaluate_crackle) and stores it as c, instead of
+ * starting from c = 0; it enters the first step's predictions. Adds 104 bytes per
+ * body to the workspace. */
+#define NB_FLAG_START_CRACKLE 1
+
 typedef struct {
     int64_t n;            /* number of bodies, 1 <= n <= 2^30 */
     double eps;           /* Plummer softening length, >= 0 */
@@ -80,7 +86,7 @@ typedef struct {
     int32_t dt_min_log2;  /* tick size and smallest step 2^dt_min_log2;
                              0 <= dt_max_log2 - dt_min_log2 <= 62 */
     int32_t precision;    /* nb_precision of nb_evaluate */
-    int32_t reserved;     /* must be 0 */
+    int32_t flags;        /* 0 or NB_FLAG_START_CRACKLE */
     int64_t partial_slots;/* capacity of the j-split partial-sum buffer in
                              (split x active body) units; 0 = default max(4n, 2^20) */
     void *stream;         /* hipStream_t for every launch; NULL = the null stream */
@@ -155,6 +161,18 @@ nb_status nb_get_predicted(nb_ctx *ctx, double *d_xp, double *d_vp, double *d_ap
  * nb_create. The result is kept for nb_correct and, if d_out is not NULL, also
  * written to d_out[10][n_act]. n_act = 0 is a no-op. Asynchronous. */
 nb_status nb_evaluate(nb_ctx *ctx, const int32_t *d_idx, int64_t n_act, double *d_out);
+
+/* The evaluation extended by one derivative (FP64 in either precision): for the
+ * active bodies idx, acceleration, jerk, snap, crackle and potential,
+ *   C = m3 jj - 9 alpha S - 9 beta J - 3 gamma A,
+ *   gamma = (3 v.a + r.jj) / R + alpha (3 beta - 4 alpha^2),
+ * the time derivative of the snap term along the relative motion with jerk jj (the
+ * derivative chain of the 6th-order Hermite scheme of the paper's section "Code
+ * implementation", continued one order). The bodies' jerks are predicted to the
+ * time of the last nb_predict (jp = j + h s + h^2/2 c). Output d_out[13][n_act]:
+ * a(3), j(3), s(3), crackle(3), phi. Needs a prior nb_predict (NB_ERR_STATE);
+ * idx as nb_evaluate. Does not feed nb_correct. Stream-ordered. */
+nb_status nb_evaluate_crackle(nb_ctx *c, const int32_t *d_idx, int64_t n_act, double *d_out);
 
 /* Supply the evaluation of the bodies d_idx from outside instead of nb_evaluate:
  * d_in[10][n_act] (same layout as nb_evaluate's output) becomes the result that

@@ -19,9 +19,10 @@ from __future__ import annotations
 import ctypes
 
 from . import _abi
-from ._abi import NB_FP64, NB_SPLIT, NBodyError
+from ._abi import NB_FLAG_START_CRACKLE, NB_FP64, NB_SPLIT, NBodyError
 
-__all__ = ["Simulation", "Batch", "NBodyError", "NB_FP64", "NB_SPLIT", "workspace_bytes",
+__all__ = ["Simulation", "Batch", "NBodyError", "NB_FP64", "NB_SPLIT", "NB_FLAG_START_CRACKLE",
+           "workspace_bytes",
            "batch_workspace_bytes"]
 
 
@@ -38,7 +39,7 @@ def workspace_bytes(n, precision=NB_FP64, partial_slots=0, eps=1e-4, eta=0.45, e
                     dt_max_log2=-3, dt_min_log2=-40):
     lib = _abi.load()
     p = _abi.Params(n=n, eps=eps, eta=eta, eta_init=eta_init, dt_max_log2=dt_max_log2,
-                    dt_min_log2=dt_min_log2, precision=precision, reserved=0,
+                    dt_min_log2=dt_min_log2, precision=precision, flags=0,
                     partial_slots=partial_slots, stream=None)
     out = ctypes.c_size_t(0)
     rc = lib.nb_workspace_bytes(ctypes.byref(p), ctypes.byref(out))
@@ -51,7 +52,7 @@ class Simulation:
     """One N-body system resident on one GPU."""
 
     def __init__(self, n, eps=1e-4, eta=0.45, eta_init=0.01, dt_max_log2=-3, dt_min_log2=-40,
-                 precision=NB_FP64, partial_slots=0, device=None, stream=None):
+                 precision=NB_FP64, partial_slots=0, device=None, stream=None, flags=0):
         torch = _torch()
         if not torch.cuda.is_available():
             raise RuntimeError("paper_1812_00367_amd needs a ROCm GPU; none is visible")
@@ -68,7 +69,7 @@ class Simulation:
         self._params = _abi.Params(n=self.n, eps=self.eps, eta=float(eta),
                                    eta_init=float(eta_init), dt_max_log2=self.dt_max_log2,
                                    dt_min_log2=self.dt_min_log2, precision=self.precision,
-                                   reserved=0, partial_slots=int(partial_slots),
+                                   flags=int(flags), partial_slots=int(partial_slots),
                                    stream=ctypes.c_void_p(self.stream.cuda_stream))
         nbytes = ctypes.c_size_t(0)
         rc = self._lib.nb_workspace_bytes(ctypes.byref(self._params), ctypes.byref(nbytes))
@@ -211,6 +212,17 @@ class Simulation:
         self._check(self._lib.nb_set_evaluation(self._ctx, _ptr(idx), idx.shape[0], _ptr(values)))
         self._eval_idx = idx
         self._eval_in = values
+
+    def evaluate_crackle(self, idx, out=None):
+        """a, j, s, crackle, phi of the bodies idx: returns out[13][n_act] (float64)."""
+        torch = _torch()
+        idx = self._dev(idx, torch.int32, (-1,))
+        n_act = idx.shape[0]
+        if out is None:
+            out = torch.empty((13, n_act), dtype=torch.float64, device=self.device)
+        self._check(self._lib.nb_evaluate_crackle(self._ctx, _ptr(idx), n_act, _ptr(out)))
+        self._crk_idx = idx
+        return out
 
     def eval_config(self, cfg=None, n_act=None):
         """Force (ipl, waves, tile, splits) or restore the default (cfg None); returns the

@@ -44,6 +44,8 @@ struct Arrays {
     int32_t *act_bcnt; // [act_blocks]
     double *en_bsum;   // [2][en_blocks]
     Status *status;
+    double *jrecj;     // [n][4] predicted jerks {jx, jy, jz, 0} (crackle evaluation)
+    double *crk;       // [13][n] start-up crackle pass output, or nullptr
 };
 
 // Launch shape of one evaluation.
@@ -99,6 +101,13 @@ hipError_t launch_timesteps(const Arrays &A, int64_t n, const int32_t *idx, int6
                             int init, double eta, double eta_init, int dt_max_log2,
                             int dt_min_log2, hipStream_t st);
 hipError_t launch_active(const Arrays &A, int64_t n, int L, int32_t *idx_out, hipStream_t st);
+// Crackle evaluation (nbody_crackle.hip): predicts every body's jerk to `tick`,
+// then a, j, s, crackle, phi of idx into out[13][n_act] (FP64).
+hipError_t launch_eval_crackle(const Arrays &A, int64_t n, const int32_t *idx, int64_t n_act,
+                               double eps, int64_t partial_slots, int64_t tick, int dt_min_log2,
+                               double *out, hipStream_t st);
+// c = rows 9..11 of the crackle output out[13][n] (every body; start-up).
+hipError_t launch_store_crackle(const Arrays &A, int64_t n, const double *out, hipStream_t st);
 hipError_t launch_energy(const Arrays &A, int64_t n, double eps, int64_t partial_slots,
                          hipStream_t st);
 

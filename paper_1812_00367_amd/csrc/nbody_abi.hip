@@ -26,6 +26,7 @@ struct nb_ctx {
     bool synced;       // every body at sync_tick (nb_set_state without tick array)
     int64_t sync_tick;
     bool predicted;    // j-records hold a prediction that no correction has invalidated
+    int64_t pred_tick; // the time of that prediction
     const int32_t *eval_idx;
     int64_t eval_n;
     bool eval_valid;   // an evaluation is waiting for its correction
@@ -81,6 +82,8 @@ size_t layout(const nb_params *p, Arrays *A, char *base)
     A->act_bcnt = (int32_t *)take(4 * (size_t)nb::act_blocks(p->n));
     A->en_bsum = (double *)take(16 * (size_t)nb::en_blocks(p->n));
     A->status = (Status *)take(sizeof(Status));
+    A->jrecj = (double *)take(32 * n);
+    A->crk = (p->flags & NB_FLAG_START_CRACKLE) ? (double *)take(104 * n) : nullptr;
     return align256(off);
 }
 
@@ -106,7 +109,7 @@ const char *check_params(const nb_params *p)
     const int L = p->dt_max_log2 - p->dt_min_log2;
     if (L < 0 || L > 62) return "need 0 <= dt_max_log2 - dt_min_log2 <= 62";
     if (p->precision != NB_FP64 && p->precision != NB_SPLIT) return "precision must be NB_FP64 or NB_SPLIT";
-    if (p->reserved != 0) return "reserved must be 0";
+    if (p->flags & ~NB_FLAG_START_CRACKLE) return "unknown flags";
     if (p->partial_slots < 0) return "partial_slots must be >= 0";
     return nullptr;
 }
@@ -162,6 +165,7 @@ nb_status do_predict(nb_ctx *c, int64_t tick)
 {
     NB_HIP(c, nb::launch_predict(c->A, c->p.n, tick, c->p.dt_min_log2, c->p.precision == NB_SPLIT, c->st));
     c->predicted = true;
+    c->pred_tick = tick;
     return NB_OK;
 }
 
@@ -417,6 +421,12 @@ nb_status nb_start(nb_ctx *c)
     NB_HIP(c, nb::launch_copy_acc_to_jrec(c->A, n, split, c->st));
     if ((s = do_evaluate(c, all, n, nullptr))) return s;
     NB_HIP(c, nb::launch_start_store(c->A, n, c->st));
+    if (c->p.flags & NB_FLAG_START_CRACKLE) {
+        // third pass: crackle from the same predicted records plus the jerks just found
+        NB_HIP(c, nb::launch_eval_crackle(c->A, n, all, n, c->p.eps, partial_slots_of(&c->p), c->sync_tick,
+                                          c->p.dt_min_log2, c->A.crk, c->st));
+        NB_HIP(c, nb::launch_store_crackle(c->A, n, c->A.crk, c->st));
+    }
     NB_HIP(c, nb::launch_timesteps(c->A, n, all, n, 1, c->p.eta, c->p.eta_init, c->p.dt_max_log2,
                                    c->p.dt_min_log2, c->st));
     c->eval_valid = false;
@@ -464,6 +474,23 @@ nb_status nb_evaluate(nb_ctx *c, const int32_t *d_idx, int64_t n_act, double *d_
     if (!c->predicted)
         return fail(c, NB_ERR_STATE, "nb_evaluate needs a prediction (nb_predict) first");
     return do_evaluate(c, d_idx, n_act, d_out);
+}
+
+nb_status nb_evaluate_crackle(nb_ctx *c, const int32_t *d_idx, int64_t n_act, double *d_out)
+{
+    NB_CTX(c);
+    nb_status s = check_idx(c, d_idx, n_act);
+    if (s)
+        return s;
+    if (n_act > 0 && !d_out)
+        return fail(c, NB_ERR_ARG, "d_out is NULL");
+    if (!c->predicted)
+        return fail(c, NB_ERR_STATE, "nb_evaluate_crackle needs a prediction (nb_predict) first");
+    if ((int64_t)13 * n_act > 10 * partial_slots_of(&c->p))
+        return fail(c, NB_ERR_SPACE, "partial-sum buffer too small for %lld active bodies", (long long)n_act);
+    NB_HIP(c, nb::launch_eval_crackle(c->A, c->p.n, d_idx, n_act, c->p.eps, partial_slots_of(&c->p),
+                                      c->pred_tick, c->p.dt_min_log2, d_out, c->st));
+    return NB_OK;
 }
 
 nb_status nb_set_evaluation(nb_ctx *c, const int32_t *d_idx, int64_t n_act, const double *d_in)

@@ -38,7 +38,7 @@ def test_every_declared_symbol_is_exported(lib):
 
 def _params(**kw):
     p = dict(n=1024, eps=1e-4, eta=0.45, eta_init=0.01, dt_max_log2=-3, dt_min_log2=-40,
-             precision=0, reserved=0, partial_slots=0, stream=None)
+             precision=0, flags=0, partial_slots=0, stream=None)
     p.update(kw)
     return _abi.Params(**p)
 
@@ -53,7 +53,7 @@ def test_workspace_bytes_and_argument_checks(lib):
     assert out.value >= fp64 + 64 * 1024
     bad = [dict(n=0), dict(n=(1 << 30) + 1), dict(eps=-1.0), dict(eps=float("nan")),
            dict(eta=0.0), dict(eta_init=-1.0), dict(dt_max_log2=-3, dt_min_log2=-70),
-           dict(dt_max_log2=-3, dt_min_log2=-2), dict(precision=2), dict(reserved=1),
+           dict(dt_max_log2=-3, dt_min_log2=-2), dict(precision=2), dict(flags=2),
            dict(partial_slots=-1)]
     for kw in bad:
         assert lib.nb_workspace_bytes(ctypes.byref(_params(**kw)), ctypes.byref(out)) == 1, kw

@@ -1,0 +1,155 @@
+"""GPU parity of the crackle evaluation (nb_evaluate_crackle) and of the crackle
+start (NB_FLAG_START_CRACKLE) against the oracle, through the C ABI.
+
+Tolerances: a, j, s, phi as the plain evaluation (<= 1e-13 per-body relative
+3-vector error); crackle <= 1e-12 (its terms cancel more: the oracle pins it at
+the same level against 40-digit derivatives); the crackle start's c <= 1e-11 (its
+inputs come from two earlier passes, see the test); the crackle start takes the
+same block steps as the oracle's and ends within 1e-9 in position."""
+import sys
+
+import numpy as np
+import pytest
+
+import nbody_inputs as ni
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+DT_MIN, DT_MAX = -40, -3
+L = DT_MAX - DT_MIN
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def nb():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1812_00367_amd as nb
+    return nb
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def rel(got, ref):
+    return np.linalg.norm(got - ref, axis=0) / np.linalg.norm(ref, axis=0)
+
+
+def errors(got, ref):
+    return [rel(got[c:c + 3], ref[c:c + 3]).max() for c in (0, 3, 6, 9)] + \
+        [(np.abs(got[12] - ref[12]) / np.abs(ref[12])).max()]
+
+
+def state(n, seed):
+    ic = ni.plummer(n, seed)
+    g = ni.rng(seed + 1)
+    a = ni.plummer_mean_field_acc(ic.x)
+    j = g.normal(0, 1.0, (3, n))
+    s = g.normal(0, 3.0, (3, n))
+    c = g.normal(0, 9.0, (3, n))
+    return ic, a, j, s, c
+
+
+@pytest.mark.parametrize("eps", [1e-4, 0.0])
+@pytest.mark.parametrize("n,n_act", [(3001, 3001), (3001, 77), (4096, 1), (130, 65)])
+def test_crackle_parity_at_the_bodies_time(nb, n, n_act, eps):
+    """Prediction at the bodies' own time (h = 0): the predicted jerk is j itself."""
+    ic, a, j, s, c = state(n, 40 + n_act)
+    sim = nb.Simulation(n, eps=eps, dt_max_log2=DT_MAX, dt_min_log2=DT_MIN)
+    sim.set_state(ic.m, ic.x, ic.v, a=a, j=j, s=s, c=c, tick=np.zeros(n, np.int64),
+                  level=np.zeros(n, np.int32))
+    sim.predict(0)
+    idx = ni.active_subset(n, n_act, 7)
+    got = host(sim.evaluate_crackle(idx))
+    ref = oracle.evaluate_crackle(ic.m, ic.x, ic.v, a, j, eps, idx=idx)
+    errs = errors(got, ref)
+    say("crackle", n, n_act, eps, errs)
+    assert max(errs[0], errs[1], errs[2], errs[4]) <= 1e-13 and errs[3] <= 1e-12, errs
+    # the a, j, s, phi rows agree with nb_evaluate's to the same bar
+    plain = host(sim.evaluate(idx))
+    assert max(rel(got[k:k + 3], plain[k:k + 3]).max() for k in (0, 3, 6)) <= 1e-13
+
+
+def test_crackle_parity_with_predicted_jerks(nb):
+    """Bodies at mixed times predicted to a later block time: positions, velocities
+    and accelerations from the GPU predictor (read back), jerks from the predictor's
+    series jp = j + h s + h^2/2 c."""
+    n = 2048
+    ic, a, j, s, c = state(n, 9)
+    tick, level = ni.block_state(n, 9, L, max_level=8)
+    sim = nb.Simulation(n, eps=1e-4, dt_max_log2=DT_MAX, dt_min_log2=DT_MIN)
+    sim.set_state(ic.m, ic.x, ic.v, a=a, j=j, s=s, c=c, tick=tick, level=level)
+    tn = int(tick.max()) + (1 << (L - 8))
+    sim.predict(tn)
+    xp, vp, ap = (host(t) for t in sim.get_predicted())
+    h = (tn - tick) * 2.0 ** DT_MIN
+    jp = j + h * (s + 0.5 * h * c)
+    idx = ni.active_subset(n, 300, 3)
+    got = host(sim.evaluate_crackle(idx))
+    ref = oracle.evaluate_crackle(ic.m, xp, vp, ap, jp, 1e-4, idx=idx)
+    errs = errors(got, ref)
+    say("crackle predicted", errs)
+    assert max(errs[0], errs[1], errs[2], errs[4]) <= 1e-13 and errs[3] <= 1e-12, errs
+
+
+def test_crackle_full_size_sampled(nb):
+    n = 65536
+    ic = ni.plummer(n, 2)
+    a = ni.plummer_mean_field_acc(ic.x)
+    jk = ni.rng(3).normal(0, 1.0, (3, n))
+    sim = nb.Simulation(n, eps=1e-4, dt_max_log2=DT_MAX, dt_min_log2=DT_MIN)
+    sim.set_state(ic.m, ic.x, ic.v, a=a, j=jk, tick=np.zeros(n, np.int64), level=np.zeros(n, np.int32))
+    sim.predict(0)
+    idx = ni.active_subset(n, 8192, 21)
+    got = host(sim.evaluate_crackle(idx))
+    pick = np.unique(np.linspace(0, 8191, 256).astype(np.int64))
+    ref = oracle.evaluate_crackle(ic.m, ic.x, ic.v, a, jk, 1e-4, idx=idx[pick])
+    errs = errors(got[:, pick], ref)
+    say("crackle c2 sampled", errs)
+    assert max(errs[0], errs[1], errs[2], errs[4]) <= 1e-13 and errs[3] <= 1e-12, errs
+
+
+def test_errors(nb):
+    sim = nb.Simulation(64, eps=1e-4)
+    ic = ni.plummer(64, 1)
+    sim.set_state(ic.m, ic.x, ic.v)
+    with pytest.raises(nb.NBodyError) as e:
+        sim.evaluate_crackle(np.arange(4, dtype=np.int32))
+    assert e.value.status == 4
+
+
+def test_crackle_start_block_steps_match_oracle(nb):
+    n = 1024
+    ic = ni.plummer(n, 1)
+    t_end = 1 << L
+    sim = nb.Simulation(n, eps=1e-4, dt_max_log2=DT_MAX, dt_min_log2=DT_MIN,
+                        flags=nb.NB_FLAG_START_CRACKLE)
+    sim.set_state(ic.m, ic.x, ic.v)
+    sim.start()
+    st0 = {k: host(v) for k, v in sim.get_state().items()}
+    ost = oracle.State(m=ic.m, x=ic.x, v=ic.v)
+    oracle.integrate(ost, 1e-4, 0.45, 0.01, DT_MAX, DT_MIN, 0, start_crackle=True)
+    # the start pass takes a and j from the two earlier passes, each within 1e-13 of
+    # the oracle's; crackle sums relative jerks with cancellation, which amplifies
+    # those differences (measured 1.0e-12 at most): the bar here is 1e-11
+    crel = rel(st0["c"], ost.c)
+    say("start crackle max rel", crel.max())
+    assert crel.max() <= 1e-11
+    steps, log, inter = sim.integrate(t_end)
+    ost = oracle.State(m=ic.m, x=ic.x, v=ic.v)
+    osteps, ostt, osna, _ = oracle.integrate(ost, 1e-4, 0.45, 0.01, DT_MAX, DT_MIN, t_end,
+                                             start_crackle=True)
+    st = {k: host(v) for k, v in sim.get_state().items()}
+    say("crackle start steps gpu/oracle", steps, osteps)
+    assert steps == osteps
+    assert np.array_equal(np.array([t for t, _ in log]), ostt)
+    assert np.array_equal(np.array([k for _, k in log]), osna)
+    assert np.abs(st["x"] - ost.x).max() < 1e-9
