@@ -245,7 +245,7 @@ typedef struct {
     int32_t precision;     /* nb_precision of the evaluation */
     double eps, eta, eta_init;        /* as in nb_params, shared by every job */
     int32_t dt_max_log2, dt_min_log2; /* as in nb_params */
-    int32_t jchunk;        /* j-records per lane of a work item (multiple of 64; 0 = 128):
+    int32_t jchunk;        /* j-records per lane of a work item (multiple of 64; 0 = 64):
                               sets a job's j-chunks, S = ceil(n / (jchunk W)) where W lanes
                               share an active body (W = 64 / next power of two >= n_act for
                               n_act < 64, else 1) */

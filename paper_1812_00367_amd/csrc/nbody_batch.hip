@@ -1012,7 +1012,7 @@ namespace {
 
 size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-constexpr int kDefaultLaneRecs = 128;
+constexpr int kDefaultLaneRecs = 64;
 constexpr int kDefaultTarget = 2048;
 
 int b_lane_recs(const nb_batch_params *p) { return p->jchunk > 0 ? p->jchunk : kDefaultLaneRecs; }

@@ -234,3 +234,33 @@ def test_batch_failing_job_is_isolated(nb):
         alone = states(b1, [k])[k]
         for key in alone:
             assert np.array_equal(alone[key], mixed[j][key]), key
+
+
+# ------------------------------------------------------ multi-step calls ------
+def test_run_steps_equals_single_steps(nb):
+    """nb_batch_run (many steps, one wait) gives bitwise the states of the same number
+    of nb_batch_step calls, and counts the same interactions."""
+    ics = [cluster(n, 300 + n) for n in (90, 700, 1300)]
+    t_end = 1 << L
+    b1 = make_batch(nb, 4096, 4)
+    b2 = make_batch(nb, 4096, 4)
+    j1 = [b1.add(ic.m, ic.x, ic.v, t_end) for ic in ics]
+    j2 = [b2.add(ic.m, ic.x, ic.v, t_end) for ic in ics]
+    inter1 = 0
+    for _ in range(40):
+        inter1 += b1.step()[3]
+    nact, tnext, err, inter2, taken = b2.run_steps(40)
+    assert inter2 == inter1 and taken == 40
+    s1, s2 = states(b1, j1), states(b2, j2)
+    for a, c in zip(j1, j2):
+        for k in s1[a]:
+            assert np.array_equal(s1[a][k], s2[c][k]), k
+    # finishing with big calls: the last call reports fewer steps than asked
+    total = 40
+    while True:
+        *_, it, taken = b2.run_steps(64)
+        total += taken
+        if taken < 64:
+            break
+    steps_alone, _, _ = run_to_end(b1)
+    assert total == 40 + steps_alone
