@@ -298,6 +298,7 @@ def energy_leg(restore, one_step, n, seconds):
         inter += one_step() * n
     torch.cuda.synchronize()
     rec = meter.stop()
+    meter.close()
     rec.update({"steps": steps, "interactions": inter,
                 "nJ": rec["joules"] / inter * 1e9 if rec.get("joules") else None,
                 "interactions_per_joule": inter / rec["joules"] if rec.get("joules") else None})

@@ -49,7 +49,9 @@ class Batch:
         self.device = torch.device(device if device is not None else "cuda")
         if self.device.index is None:
             self.device = torch.device("cuda", torch.cuda.current_device())
-        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        # a stream of its own by default (default priority): a multi-step call replays a
+        # captured HIP graph of one batch step, and the null stream cannot be captured
+        self.stream = stream if stream is not None else torch.cuda.Stream(self.device)
         self.capacity = int(capacity)
         self.max_jobs = int(max_jobs)
         self.dt_min_log2 = int(dt_min_log2)
@@ -71,6 +73,7 @@ class Batch:
         self._raw = raw
         self._ws = raw[off:off + nbytes.value]
         ctx = ctypes.c_void_p(0)
+        self._order()
         rc = self._lib.nb_batch_create(ctypes.byref(self._params), _ptr(self._ws), nbytes.value,
                                        ctypes.byref(ctx))
         if rc:
@@ -85,6 +88,14 @@ class Batch:
     def _check(self, rc):
         if rc:
             raise NBodyError(rc, self._lib.nb_batch_last_error(self._ctx).decode())
+
+    def _order(self):
+        """The batch's stream waits for torch's current stream (tensors the call reads
+        or writes were made there); every call waits for its own stream on return."""
+        torch = _torch()
+        cur = torch.cuda.current_stream(self.device)
+        if cur.cuda_stream != self.stream.cuda_stream:
+            self.stream.wait_stream(cur)
 
     def close(self):
         if getattr(self, "_ctx", None):
@@ -120,6 +131,7 @@ class Batch:
                     level=self._dev(level, torch.int32, (n,)))
         view = _abi.State(**{k: (t.data_ptr() if t is not None else None) for k, t in keep.items()})
         job = ctypes.c_int32(-1)
+        self._order()
         rc = self._lib.nb_batch_add(self._ctx, n, ctypes.byref(view), int(tick0), int(tick_end),
                                     ctypes.byref(job))
         if rc == NB_ERR_SPACE:
@@ -187,6 +199,7 @@ class Batch:
         out["tick"] = torch.empty(n, dtype=torch.int64, device=self.device)
         out["level"] = torch.empty(n, dtype=torch.int32, device=self.device)
         view = _abi.State(**{k: t.data_ptr() for k, t in out.items()})
+        self._order()
         self._check(self._lib.nb_batch_get(self._ctx, int(job), ctypes.byref(view)))
         return out
 

@@ -1,7 +1,7 @@
 // nbody_batch.hip -- many independent N-body systems ("jobs") of uneven size in one
 // workspace, advanced together: every batch step gives each job its own next block
 // step (its own block time and active set, the block-step scheme of the paper's
-// section "Code implementation"), with a fixed sequence of six launches for all jobs
+// section "Code implementation"), with a fixed sequence of seven launches for all jobs
 // and no host work in between:
 //
 //   k_bact     one workgroup per job: next block time, active list (ascending);
@@ -1003,6 +1003,9 @@ struct nb_batch {
     nb::Status *h_status;
     bool jobs_dirty;    // the job list changed since it was last uploaded
     int njobs;
+    hipGraph_t graph;   // one captured batch step (multi-step calls)
+    hipGraphExec_t gexec;
+    bool graph_valid, no_graph;
     int64_t *h_nact() { return reinterpret_cast<int64_t *>(h_jobblk); }
     int64_t *h_tnext() { return reinterpret_cast<int64_t *>(h_jobblk) + p.max_jobs; }
     int32_t *h_err() { return reinterpret_cast<int32_t *>(h_jobblk + 16 * (size_t)p.max_jobs); }
@@ -1158,7 +1161,8 @@ nb_status b_eval_finish(nb_batch *b, const int32_t *list, int n_list, int mode, 
 }
 
 // One block step of every job in the batch, enqueued without waiting.
-nb_status b_enqueue_step(nb_batch *b)
+// The job list to the device when it changed since the last upload.
+nb_status b_upload_jobs(nb_batch *b)
 {
     if (b->jobs_dirty) {
         b->njobs = 0;
@@ -1168,7 +1172,14 @@ nb_status b_enqueue_step(nb_batch *b)
         if (b->njobs > 0)
             B_HIP(b, hipMemcpyAsync(b->d_jobs, b->h_jobs, 4 * (size_t)b->njobs, hipMemcpyHostToDevice, b->st));
         b->jobs_dirty = false;
+        b->graph_valid = false;  // the captured step launches a grid per listed job
     }
+    return NB_OK;
+}
+
+// The kernels of one batch step (the job list already on the device).
+nb_status b_launch_step(nb_batch *b)
+{
     if (b->njobs == 0)
         return NB_OK;
     const bool split = b->p.precision == NB_SPLIT;
@@ -1178,6 +1189,54 @@ nb_status b_enqueue_step(nb_batch *b)
                        ldexp(1.0, b->p.dt_min_log2), (int)split);
     B_HIP(b, hipGetLastError());
     return b_eval_finish(b, b->d_jobs, b->njobs, nb::kStep, 1);
+}
+
+nb_status b_enqueue_step(nb_batch *b)
+{
+    nb_status s = b_upload_jobs(b);
+    return s ? s : b_launch_step(b);
+}
+
+void b_drop_graph(nb_batch *b)
+{
+    if (b->gexec)
+        (void)hipGraphExecDestroy(b->gexec);
+    if (b->graph)
+        (void)hipGraphDestroy(b->graph);
+    b->gexec = nullptr;
+    b->graph = nullptr;
+    b->graph_valid = false;
+}
+
+// Capture one batch step's launches as a graph, replayed by multi-step calls (the
+// launches carry no per-step arguments: every size comes from device memory). No
+// memset or copy is captured. Returns false (and the caller launches directly) when
+// the stream cannot be captured, e.g. the null stream.
+bool b_capture_step(nb_batch *b)
+{
+    b_drop_graph(b);
+    if (!b->st || b->no_graph)
+        return false;
+    if (hipStreamBeginCapture(b->st, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        (void)hipGetLastError();
+        b->no_graph = true;
+        return false;
+    }
+    const nb_status s = b_launch_step(b);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(b->st, &g);
+    if (s != NB_OK || e != hipSuccess || !g ||
+        hipGraphInstantiate(&b->gexec, g, nullptr, nullptr, 0) != hipSuccess) {
+        if (g)
+            (void)hipGraphDestroy(g);
+        b->gexec = nullptr;
+        (void)hipGetLastError();
+        b->no_graph = true;
+        return false;
+    }
+    b->graph = g;
+    b->graph_valid = true;
+    return true;
 }
 
 // Job table and step header to the host (one wait).
@@ -1295,6 +1354,7 @@ void nb_batch_destroy(nb_batch *b)
     if (!b)
         return;
     (void)hipStreamSynchronize(b->st);
+    b_drop_graph(b);
     for (void *q : {(void *)b->h_scalar, (void *)b->h_jobblk, (void *)b->h_hdr, (void *)b->h_jobs,
                     (void *)b->h_status})
         if (q)
@@ -1428,9 +1488,16 @@ nb_status nb_batch_run(nb_batch *b, int32_t steps, int64_t *h_n_act, int64_t *h_
         return bfail(b, NB_ERR_ARG, "steps must be >= 1");
     nb_status s;
     const int64_t inter0 = b->h_hdr->inter, steps0 = b->h_hdr->steps;
-    for (int k = 0; k < steps; ++k)
-        if ((s = b_enqueue_step(b)))
-            return s;
+    if ((s = b_upload_jobs(b)))
+        return s;
+    if (b->njobs > 0 && steps > 1 && (b->graph_valid || b_capture_step(b))) {
+        for (int k = 0; k < steps; ++k)
+            B_HIP(b, hipGraphLaunch(b->gexec, b->st));
+    } else {
+        for (int k = 0; k < steps; ++k)
+            if ((s = b_launch_step(b)))
+                return s;
+    }
     if ((s = b_fetch(b)))
         return s;
     b_outputs(b, h_n_act, h_tick_next, h_job_err);

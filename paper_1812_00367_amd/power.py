@@ -99,6 +99,15 @@ class EnergyMeter:
         self._thr = threading.Thread(target=self._sample, daemon=True)
         self._thr.start()
 
+    def close(self):
+        if self._smi is not None:
+            try:
+                self._smi.amdsmi_shut_down()
+            except Exception:  # noqa: BLE001
+                pass
+            self._smi = None
+            self.available = False
+
     def stop(self):
         if not self.available:
             return {"joules": None, "avg_power_w": None, "samples": 0, "reason": self.reason}

@@ -264,3 +264,34 @@ def test_run_steps_equals_single_steps(nb):
             break
     steps_alone, _, _ = run_to_end(b1)
     assert total == 40 + steps_alone
+
+
+# ------------------------------------------------ many small jobs, eps = 0 ------
+def test_many_small_jobs_and_unsoftened(nb):
+    """1500 jobs of 2..40 bodies: the work split and its prefix sums run over more
+    than one 1024-job pass, and the item / body searches leave the 1024-entry LDS
+    cache for global memory. eps = 0 exercises the self-pair mask. Every job must
+    take the oracle's block steps; a sample is compared in full."""
+    g = ni.rng(91)
+    sizes = [int(v) for v in g.integers(2, 41, 1500)]
+    t_end = 1 << L
+    b = make_batch(nb, sum(sizes), 1500, eps=0.0)
+    ics = []
+    jobs = []
+    for k, n in enumerate(sizes):
+        ic = ni.plummer(n, 5000 + k)
+        ics.append(ic)
+        jobs.append(b.add(ic.m, ic.x, ic.v, t_end))
+    assert all(j is not None for j in jobs)
+    steps, inter, logs = run_to_end(b)
+    say("many small jobs: batch steps", steps, "interactions", inter)
+    for k in list(range(0, 1500, 97)) + [1499]:
+        j, ic = jobs[k], ics[k]
+        ost = oracle.State(m=ic.m, x=ic.x, v=ic.v)
+        osteps, ostt, osna, _ = oracle.integrate(ost, 0.0, 0.45, 0.01, DT_MAX, DT_MIN, t_end)
+        gt = np.array([t for t, _ in logs[j]])
+        gn = np.array([x for _, x in logs[j]])
+        assert len(gt) == osteps and np.array_equal(gt, ostt) and np.array_equal(gn, osna), k
+        st = {key: host(v) for key, v in b.get(j).items()}
+        assert np.array_equal(st["level"], ost.level), k
+        assert np.abs(st["x"] - ost.x).max() < 1e-9, k
