@@ -228,7 +228,7 @@ nb_status nb_energy(nb_ctx *ctx, int64_t tick, double *h_ekin, double *h_epot);
  * Many independent systems ("jobs") of uneven size resident in one workspace and
  * advanced together (block steps as in the paper's section "Code implementation").
  * A batch step gives each job its own next block step (its own block time and
- * active set, as nb_step does for one system) with six kernel launches for all
+ * active set, as nb_step does for one system) with seven kernel launches for all
  * jobs and no host work in between: active sets, prediction, a work split, a
  * persistent evaluation over work items (job, i-tile of up to 64 active bodies,
  * j-chunk) in two item classes, and a per-body pass that sums the partials in a
