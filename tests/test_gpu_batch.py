@@ -295,3 +295,22 @@ def test_many_small_jobs_and_unsoftened(nb):
         st = {key: host(v) for key, v in b.get(j).items()}
         assert np.array_equal(st["level"], ost.level), k
         assert np.abs(st["x"] - ost.x).max() < 1e-9, k
+
+
+# --------------------------------------------- split precision against the oracle --
+def test_batch_split_startup_within_rounding_bound(nb):
+    """The batch path's split-precision evaluation (tile and direct classes) at the
+    Hermite start-up of jobs of 5..1500 bodies, against the FP64 oracle evaluated on
+    the same inputs (positions, velocities, and the start-up accelerations read
+    back), within the FP32 rounding bound of the split-precision tests."""
+    from test_gpu_split import check_split, envelope
+    sizes = [5, 70, 300, 1500]
+    b = make_batch(nb, sum(sizes), 4, precision=nb.NB_SPLIT)
+    for k, n in enumerate(sizes):
+        ic = cluster(n, 700 + k)
+        j = b.add(ic.m, ic.x, ic.v, 1 << L)
+        st = {key: host(v) for key, v in b.get(j).items()}
+        got = np.concatenate([st["a"], st["j"], st["s"], st["phi"][None, :]])
+        ref = oracle.evaluate(ic.m, ic.x, ic.v, st["a"], 1e-4)
+        env = envelope(ic.m, ic.x, ic.v, st["a"], 1e-4, np.arange(n))
+        check_split(got, ref, env, f"batch split n={n}")
