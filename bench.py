@@ -40,13 +40,16 @@ EPS = 1e-4
 DT_MAX, DT_MIN = -3, -40
 SWEEP = (1, 64, 1024, 8192, 65536)
 METRIC = "pairwise interactions/s (acc+jerk+snap) and % of FP64/FP32 vector peak; p99"
-PEAK_FP32_TFLOPS = 157.3           # packed FP32; unpacked FP32 issues at the FP64 rate
+PEAK_FP32_TFLOPS = 157.3           # the chip's FP32 vector peak (packed instructions)
 # sources of the evaluation kernel; the traffic figure below is valid only for them
 KERNEL_SRCS = [os.path.join(ROOT, "paper_1812_00367_amd", "csrc", f)
                for f in ("nbody_kernels.hip", "nb_device.h", "nb_internal.h")]
 # HBM bytes per full-N FP64 evaluation launch from the FETCH_SIZE / WRITE_SIZE runs in
 # profiles/eval_fp64_plummer65536.md, keyed by the sha256 prefix of those sources.
 TRAFFIC = {"f8fe6ef99232d70e": {"fp64": 2.00 * 21978 * 1024 + 81920 * 1024}}
+# Flops per interaction the evaluation kernels execute (SQ_INSTS_VALU_FLOPS_FP64 /
+# _FP32 x 64 lanes / N^2, same profile), keyed the same way.
+EXECUTED_FLOPS = {"f8fe6ef99232d70e": {"fp64": 88.0, "split": 86.0}}
 
 
 def kernel_sources_hash():
@@ -212,6 +215,7 @@ def main():
     value = inter / elapsed
     src_hash = kernel_sources_hash()
     traffic = TRAFFIC.get(src_hash, {}).get(args.precision) if n == N_BODIES else None
+    executed = EXECUTED_FLOPS.get(src_hash, {}).get(args.precision)
 
     result = {
         "metric": METRIC,
@@ -234,7 +238,9 @@ def main():
                      "kernel": "k_eval_f64" if prec == nb.NB_FP64 else "k_eval_split",
                      "flop_per_interaction": FLOP_PER_INTERACTION,
                      "algorithmic_bytes": 80 * n + 152 * n,
-                     "eval_ms_avg": eval_avg_s * 1e3, "kernel_src": src_hash},
+                     "eval_ms_avg": eval_avg_s * 1e3, "kernel_src": src_hash,
+                     "executed_flop_per_interaction": executed,
+                     "executed_tflops": None if executed is None else executed * n * n / eval_avg_s / 1e12},
         "energy": {"ekin": ek, "epot": ep, "ms": t_energy * 1e3},
     }
 
