@@ -10,8 +10,8 @@
 //              place its work items, partial sums and active bodies;
 //   k_beval    persistent waves taking work items (job, i-tile, j-chunk) until none
 //              is left (two launches, one per item class);
-//   k_bfinish  one thread per active body: fixed-order sum of its partials, corrector,
-//              new step level.
+//   k_bfinish  four lanes per active body: fixed-order sum of its partials,
+//              corrector, new step level.
 //
 // Pool layout: job j owns the contiguous body range [off_j, off_j + n_j) of a pool of
 // `capacity` bodies; vectors are [3][capacity] structure-of-arrays and the j-records
@@ -176,10 +176,14 @@ __host__ __device__ inline int item_lanes(int64_t rem)
 }
 
 // Split of one job's evaluation: tiles = ceil(n_act / 64) i-tiles (of 128 for a wide
-// job, n_act >= wide_min), S j-chunks of jch bodies. S gives every lane about `lane_recs` records (lane_recs 16 / W when W > 16
-// lanes share a body, so that a job with one to three active bodies still spreads
-// over several waves), but no more chunks than make `target` work items for the job.
-// Depends on (n, n_act) and the batch constants only.
+// job, n_act >= wide_min), S j-chunks of jch bodies. S gives every lane about
+// `lane_recs` records (lane_recs 16 / W when W > 16 lanes share a body, so that a job
+// with one to three active bodies still spreads over several waves; kWideRecs x
+// lane_recs in a wide item, whose 128 bodies amortise a longer chunk and write a
+// quarter of the partial sums), but no more chunks than make `target` work items for
+// the job. Depends on (n, n_act) and the batch constants only.
+constexpr int kWideRecs = 4;
+
 struct JobSplit {
     int64_t tiles, S, jch;
     bool wide;
@@ -193,7 +197,7 @@ __host__ __device__ inline JobSplit job_split(int64_t n, int64_t na, int lane_re
     const int64_t tw = r.wide ? 2 * kItemTile : kItemTile;
     r.tiles = (na + tw - 1) / tw;
     const int64_t W = r.wide ? 1 : item_lanes(na < 64 ? na : 64);
-    const int64_t per = (int64_t)lane_recs * (W < 16 ? W : 16);  // bodies per chunk
+    const int64_t per = (int64_t)lane_recs * (r.wide ? kWideRecs : (W < 16 ? W : 16));  // bodies per chunk
     int64_t S = (n + per - 1) / per;
     const int64_t cap = (target + r.tiles - 1) / r.tiles;
     S = S < cap ? S : cap;
@@ -799,7 +803,14 @@ __global__ __launch_bounds__(64) void k_beval_split(Pool P, float eps2)
 //   kStep:    Hermite corrector over the step, phi and time, new level.
 enum FinishMode : int { kStartA = 0, kStartB = 1, kStep = 2 };
 
-constexpr int kFinLanes = 16;  // lanes that share one body's partial-sum reduction
+// Four lanes share one active body: a wave takes 16 consecutive active bodies (in
+// the plan's global order), lane l * 16 + b summing chunks l, l + 4, ... of body b in
+// ascending order, so the 16 lanes of each quarter read 16 consecutive slots (128
+// bytes) of one chunk row. The four lane sums are then added by a fixed butterfly
+// (l ^ 2, then l ^ 1), and the lanes with l = 0 apply the result. The order depends
+// on S only.
+constexpr int kFinLanes = 4;
+constexpr int kFinPerWave = 64 / kFinLanes;
 
 __global__ __launch_bounds__(256) void k_bfinish(Pool P, int64_t cap, int mode, double tick_size,
                                                  double eta, double eta_init, int dt_max_log2, int L)
@@ -811,17 +822,17 @@ __global__ __launch_bounds__(256) void k_bfinish(Pool P, int64_t cap, int mode, 
     if ((int64_t)blockIdx.x * per_block >= total)
         return;
     const int64_t *act0 = cache_prefix(P.pl_act0, nplan, s_act0);
-    const int l = (int)threadIdx.x & (kFinLanes - 1);
-    // every lane of a group runs the same number of iterations (shuffles inside)
+    const int lane = (int)threadIdx.x & 63;
+    const int l = lane / kFinPerWave, bw = lane % kFinPerWave;
+    const int wave = (int)threadIdx.x >> 6;
+    // every lane of a wave runs the same iterations (shuffles inside)
     for (int64_t e0 = (int64_t)blockIdx.x * per_block; e0 < total; e0 += (int64_t)gridDim.x * per_block) {
-        const int64_t e = e0 + (threadIdx.x / kFinLanes);
+        const int64_t e = e0 + wave * kFinPerWave + bw;
         const bool live = e < total;
         const int q = find_entry(act0, nplan, live ? e : total - 1);
         const int job = P.pl_job[q];
         const int64_t slot = (live ? e : total - 1) - act0[q], na = P.pl_na[q], pbase = P.pl_pbase[q];
         const int S = P.pl_S[q];
-        // lane l sums chunks l, l + 16, ... in ascending order; the 16 lane sums are
-        // then added by a fixed butterfly: one fixed order for a given S
         double ev[10];
 #pragma unroll
         for (int c = 0; c < 10; ++c)
@@ -833,8 +844,10 @@ __global__ __launch_bounds__(256) void k_bfinish(Pool P, int64_t cap, int mode, 
                 ev[c] += src[(int64_t)c * na];
         }
 #pragma unroll
-        for (int c = 0; c < 10; ++c)
-            ev[c] = lane_butterfly(ev[c], kFinLanes);
+        for (int o = 32; o >= kFinPerWave; o >>= 1)
+#pragma unroll
+            for (int c = 0; c < 10; ++c)
+                ev[c] += __shfl_xor(ev[c], o, 64);
         if (!live || l != 0)
             continue;
         const int64_t off = P.j_off[job];
