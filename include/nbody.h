@@ -289,7 +289,8 @@ nb_status nb_batch_remove(nb_batch *b, int32_t job);
 /* One block step of every job whose next block time is not beyond its tick_end.
  * Host outputs indexed by job id (arrays of max_jobs entries, each may be NULL):
  * the number of bodies the job advanced (0: finished, failed or not present), its
- * next block time, and its error word (0 ok; 1 a non-finite corrector value;
+ * next block time (a finished or failed job keeps the last one computed), and its
+ * error word (0 ok; 1 a non-finite corrector value;
  * 2 a body needs a step below dt_min; 3 an inconsistent time or level). A job with
  * a non-zero error word is not stepped again; the other jobs are unaffected.
  * *h_interactions = the sum over jobs of n_act x n. */

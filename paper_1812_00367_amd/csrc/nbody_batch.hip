@@ -90,6 +90,7 @@ struct Pool {
 // tick_next is beyond the job's end time or the job has failed.
 constexpr int kBS = 1024;
 constexpr int kBW = kBS / 64;
+constexpr int kUnroll = 4;
 
 __global__ __launch_bounds__(kBS) void k_bact(Pool P, const int32_t *__restrict__ jobs, int L)
 {
@@ -97,18 +98,38 @@ __global__ __launch_bounds__(kBS) void k_bact(Pool P, const int32_t *__restrict_
     __shared__ int wc[kBW];
     __shared__ int sbad[kBW];
     const int job = jobs[blockIdx.x];
+    // a failed job, or one whose last block time reached its end (every body is then
+    // past it), does not step again: no scan
+    if (P.j_err[job] != kJobOk || P.j_tnext[job] >= P.j_tend[job]) {
+        if (threadIdx.x == 0)
+            P.j_nact[job] = 0;
+        return;
+    }
     const int64_t off = P.j_off[job], n = P.j_n[job];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     int64_t mn = INT64_MAX;
     int badlevel = 0;
-    for (int64_t k = threadIdx.x; k < n; k += kBS) {
-        int lv = P.level[off + k];
-        if (lv < 0 || lv > L) {
-            badlevel = 1;
-            lv = L;
+    // kUnroll bodies per thread per round, their loads issued together
+    for (int64_t k0 = threadIdx.x; k0 < n; k0 += kUnroll * kBS) {
+        int lv[kUnroll];
+        int64_t tk[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+            const int64_t k = k0 + u * kBS;
+            lv[u] = k < n ? P.level[off + k] : 0;
+            tk[u] = k < n ? P.tick[off + k] : INT64_MAX;
         }
-        const int64_t e = P.tick[off + k] + ((int64_t)1 << (L - lv));
-        mn = e < mn ? e : mn;
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+            if (k0 + u * kBS >= n)
+                continue;
+            if (lv[u] < 0 || lv[u] > L) {
+                badlevel = 1;
+                lv[u] = L;
+            }
+            const int64_t e = tk[u] + ((int64_t)1 << (L - lv[u]));
+            mn = e < mn ? e : mn;
+        }
     }
     mn = wave_min_i64(mn);
     badlevel = wave_max_i32(badlevel);
@@ -225,41 +246,59 @@ __host__ __device__ inline bool tail_direct(int64_t na, int64_t tiles)
     return item_lanes(na - (tiles - 1) * kItemTile) >= kDirectW;
 }
 
-// Block-wide exclusive scan of a 64-bit value (kBS threads); returns the exclusive
-// prefix and writes the block total to *total. Uses scr[kBW + 1].
-__device__ __forceinline__ int64_t block_scan(int64_t v, int64_t *scr, int64_t *total)
+// Block-wide exclusive scans of NV 64-bit values at once (kBS threads): v[k] is
+// replaced by its exclusive prefix and tot[k] receives the block total. Each wave
+// scans its lanes, wave 0 scans the kBW wave totals into pre, and every thread adds
+// its wave's prefix: three barriers in all.
+template <int NV>
+__device__ __forceinline__ void block_scan(int64_t (&v)[NV], int64_t (&tot)[NV], int64_t (*scr)[NV],
+                                           int64_t (*pre)[NV])
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    int64_t inc = v;
+    int64_t inc[NV];
 #pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        const int64_t u = __shfl_up(inc, o, 64);
-        if (lane >= o)
-            inc += u;
-    }
-    if (lane == 63)
-        scr[wave] = inc;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int64_t acc = 0;
-        for (int w = 0; w < kBW; ++w) {
-            const int64_t t = scr[w];
-            scr[w] = acc;
-            acc += t;
+    for (int k = 0; k < NV; ++k)
+        inc[k] = v[k];
+    for (int o = 1; o < 64; o <<= 1)
+#pragma unroll
+        for (int k = 0; k < NV; ++k) {
+            const int64_t u = __shfl_up(inc[k], o, 64);
+            if (lane >= o)
+                inc[k] += u;
         }
-        scr[kBW] = acc;
+    if (lane == 63)
+#pragma unroll
+        for (int k = 0; k < NV; ++k)
+            scr[wave][k] = inc[k];
+    __syncthreads();
+    if (wave == 0) {
+        // lane w <= kBW: sum of the totals of waves before w (lane kBW: all of them)
+#pragma unroll
+        for (int k = 0; k < NV; ++k) {
+            int64_t x = lane < kBW ? scr[lane][k] : 0;
+            for (int o = 1; o < 32; o <<= 1) {
+                const int64_t u = __shfl_up(x, o, 64);
+                if (lane >= o)
+                    x += u;
+            }
+            const int64_t ex = __shfl_up(x, 1, 64);
+            if (lane <= kBW)
+                pre[lane][k] = lane == 0 ? 0 : ex;
+        }
     }
     __syncthreads();
-    const int64_t ex = scr[wave] + inc - v;
-    *total = scr[kBW];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+        v[k] = pre[wave][k] + inc[k] - v[k];
+        tot[k] = pre[kBW][k];
+    }
     __syncthreads();
-    return ex;
 }
 
 __global__ __launch_bounds__(kBS) void k_plan(Pool P, const int32_t *__restrict__ jobs, int njobs,
                                               int lane_recs, int target, int64_t wide_min, int count)
 {
-    __shared__ int64_t scr[7][kBW + 1];
+    __shared__ int64_t scr[kBW][7], pre[kBW + 1][7];
     int64_t c_plan = 0, c_it[kClasses] = {0, 0, 0}, c_act = 0, c_ps = 0, c_inter = 0;
     for (int base = 0; base < njobs; base += kBS) {
         const int p = base + (int)threadIdx.x;
@@ -279,13 +318,13 @@ __global__ __launch_bounds__(kBS) void k_plan(Pool P, const int32_t *__restrict_
         const int64_t tail_d = on && !sp.wide && tail_direct(na, sp.tiles) ? 1 : 0;
         const int64_t n_items[kClasses] = {sp.wide ? 0 : (sp.tiles - tail_d) * sp.S,
                                            sp.wide ? sp.tiles * sp.S : 0, tail_d * sp.S};
-        int64_t t_plan, t_it[kClasses], x_it[kClasses], t_act, t_ps, t_int;
-        const int64_t x_plan = block_scan(on ? 1 : 0, scr[0], &t_plan);
-        for (int k = 0; k < kClasses; ++k)
-            x_it[k] = block_scan(n_items[k], scr[1 + k], &t_it[k]);
-        const int64_t x_act = block_scan(na, scr[4], &t_act);
-        const int64_t x_ps = block_scan(sp.S * na, scr[5], &t_ps);
-        block_scan(na * n, scr[6], &t_int);
+        // exclusive prefixes and totals of: stepping jobs, items of each class, active
+        // bodies, partial-sum slots, interactions
+        int64_t x[7] = {on ? 1 : 0, n_items[0], n_items[1], n_items[2], na, sp.S * na, na * n}, t[7];
+        block_scan<7>(x, t, scr, pre);
+        const int64_t x_plan = x[0], x_it[kClasses] = {x[1], x[2], x[3]}, x_act = x[4], x_ps = x[5];
+        const int64_t t_plan = t[0], t_it[kClasses] = {t[1], t[2], t[3]}, t_act = t[4], t_ps = t[5],
+                      t_int = t[6];
         if (on) {
             const int64_t q = c_plan + x_plan;
             P.pl_job[q] = job;
