@@ -1,7 +1,7 @@
 // nbody_batch.hip -- many independent N-body systems ("jobs") of uneven size in one
 // workspace, advanced together: every batch step gives each job its own next block
 // step (its own block time and active set, the block-step scheme of the paper's
-// section "Code implementation"), with a fixed sequence of seven launches for all jobs
+// section "Code implementation"), with a fixed sequence of five launches for all jobs
 // and no host work in between:
 //
 //   k_bact     one workgroup per job: next block time, active list (ascending);
@@ -9,7 +9,7 @@
 //   k_plan     one workgroup: each stepping job's work split and the prefix sums that
 //              place its work items, partial sums and active bodies;
 //   k_beval    persistent waves taking work items (job, i-tile, j-chunk) until none
-//              is left (two launches, one per item class);
+//              is left, class after class (three item classes in FP64, two in split);
 //   k_bfinish  four lanes per active body: fixed-order sum of its partials,
 //              corrector, new step level.
 //
@@ -609,22 +609,33 @@ __device__ __forceinline__ void sweep_lds_f64(const double2 *__restrict__ src, i
     }
 }
 
-// Persistent: wave b takes item b of its class first, then further items from the
-// step's counter (numbered from the grid size on) until none is left, so the first
-// round needs no atomic and later ones balance uneven item costs.
-template <int CLS>
-__global__ __launch_bounds__(64) void k_beval_f64(Pool P, double eps2)
+// Work items are taken persistently. In a class claimed statically, wave b takes
+// item b first and further items come from the class's counter numbered from the
+// grid size on (the first round needs no atomic); in a class claimed dynamically
+// every item comes from the counter, so a wave still busy elsewhere holds none back.
+__device__ __forceinline__ int64_t claim_item(const Pool &P, int cls, int64_t base)
 {
-    constexpr bool kLds = CLS != kClassDirect;
-    __shared__ double2 lds[kLds ? 2 : 1][kLds ? kItemTile * 5 : 1];
-    __shared__ int64_t s_item0[kPlanCache];
+    unsigned int got = 0;
+    if (threadIdx.x == 0)
+        got = atomicAdd(&P.hdr->counter[cls], 1u);
+    return base + (int64_t)__shfl(got, 0, 64);
+}
+
+// The items of one class (first: claimed statically).
+template <int CLS>
+__device__ __forceinline__ void eval_items_f64(const Pool &P, double eps2, double2 (*lds)[kItemTile * 5],
+                                               int64_t *s_item0, bool first)
+{
     const int64_t nitems = P.hdr->nitems[CLS];
     const int nplan = P.hdr->nplan;
-    if ((int64_t)blockIdx.x >= nitems)  // the other waves drain every item
+    const int64_t base = first ? (int64_t)gridDim.x : 0;
+    int64_t item = first ? (int64_t)blockIdx.x : (nitems > 0 ? claim_item(P, CLS, 0) : 0);
+    if (item >= nitems)  // the other waves drain every item
         return;
+    __syncthreads();  // the previous class is done with s_item0
     const int64_t *item0 = cache_prefix(P.pl_item0[CLS], nplan, s_item0);
     const double2 *__restrict__ src = reinterpret_cast<const double2 *>(P.jrec);
-    for (int64_t item = blockIdx.x; item < nitems;) {
+    while (item < nitems) {
         const Item it = decode_item<CLS>(P, item0, nplan, item);
         if constexpr (CLS == kClassWide) {
             // two active bodies per lane (slots ibase + lane and ibase + 64 + lane)
@@ -668,11 +679,23 @@ __global__ __launch_bounds__(64) void k_beval_f64(Pool P, double eps2)
                               reinterpret_cast<double2 (*)[kItemTile * 5]>(&lds[0][0]));
             finish_item(P, b, it, bad);
         }
-        unsigned int got = 0;
-        if (threadIdx.x == 0)
-            got = atomicAdd(&P.hdr->counter[CLS], 1u);
-        item = (int64_t)gridDim.x + (int64_t)__shfl(got, 0, 64);
+        item = claim_item(P, CLS, base);
     }
+}
+
+// All FP64 items of a step in one launch, class after class, so a wave that runs out
+// of one class moves on while others finish theirs: first the direct class (few
+// items, bound by load latency, which then overlaps the arithmetic of the others),
+// then the wide class (the longest items), both claimed statically, then the tile
+// class, claimed dynamically as waves come free (statically when it is alone).
+__global__ __launch_bounds__(64) void k_beval_f64(Pool P, double eps2)
+{
+    __shared__ double2 lds[2][kItemTile * 5];
+    __shared__ int64_t s_item0[kPlanCache];
+    const bool tile_alone = P.hdr->nitems[kClassDirect] == 0 && P.hdr->nitems[kClassWide] == 0;
+    eval_items_f64<kClassDirect>(P, eps2, lds, s_item0, true);
+    eval_items_f64<kClassWide>(P, eps2, lds, s_item0, true);
+    eval_items_f64<kClassTile>(P, eps2, lds, s_item0, tile_alone);
 }
 
 // ------------------------------------------------------ split-precision path ----
@@ -788,21 +811,22 @@ __device__ __forceinline__ void sweep_lds_split(const float4 *__restrict__ src, 
 }
 
 template <int CLS>
-__global__ __launch_bounds__(64) void k_beval_split(Pool P, float eps2)
+__device__ __forceinline__ void eval_items_split(const Pool &P, float eps2, float4 (*lds)[kItemTile * 4],
+                                                 int64_t *s_item0, bool first)
 {
     static_assert(CLS != kClassWide, "the split path has no wide class");
     constexpr bool DIRECT = CLS == kClassDirect;
-    __shared__ float4 lds[DIRECT ? 1 : 2][DIRECT ? 1 : kItemTile * 4];
-    __shared__ int64_t s_item0[kPlanCache];
     constexpr int cls = CLS;
     const int64_t nitems = P.hdr->nitems[cls];
     const int nplan = P.hdr->nplan;
-    if ((int64_t)blockIdx.x >= nitems)  // the other waves drain every item
+    const int64_t base = first ? (int64_t)gridDim.x : 0;
+    int64_t item = first ? (int64_t)blockIdx.x : (nitems > 0 ? claim_item(P, cls, 0) : 0);
+    if (item >= nitems)  // the other waves drain every item
         return;
+    __syncthreads();  // the previous class is done with s_item0
     const int64_t *item0 = cache_prefix(P.pl_item0[cls], nplan, s_item0);
     const float4 *__restrict__ src = reinterpret_cast<const float4 *>(P.jrec32);
-    // the first item of each wave is its own index; later ones come from the counter
-    for (int64_t item = blockIdx.x; item < nitems;) {
+    while (item < nitems) {
         const Item it = decode_item<CLS>(P, item0, nplan, item);
         bool bad;
         const int i = item_body(P, it, &bad);
@@ -828,11 +852,18 @@ __global__ __launch_bounds__(64) void k_beval_split(Pool P, float eps2)
             sweep_lds_split(src, it.jbeg, it.jend, it.W, it.lw, it.w, b, lo, hi, eps2,
                             reinterpret_cast<float4 (*)[kItemTile * 4]>(&lds[0][0]));
         finish_item(P, b, it, bad);
-        unsigned int got = 0;
-        if (threadIdx.x == 0)
-            got = atomicAdd(&P.hdr->counter[cls], 1u);
-        item = (int64_t)gridDim.x + (int64_t)__shfl(got, 0, 64);
+        item = claim_item(P, cls, base);
     }
+}
+
+// All split-precision items of a step in one launch (direct class, then tile class,
+// in the same way as the FP64 launch).
+__global__ __launch_bounds__(64) void k_beval_split(Pool P, float eps2)
+{
+    __shared__ float4 lds[2][kItemTile * 4];
+    __shared__ int64_t s_item0[kPlanCache];
+    eval_items_split<kClassDirect>(P, eps2, lds, s_item0, true);
+    eval_items_split<kClassTile>(P, eps2, lds, s_item0, P.hdr->nitems[kClassDirect] == 0);
 }
 
 // ------------------------------------------------- per active body: finishing ----
@@ -1040,7 +1071,7 @@ struct nb_batch {
     Pool P;
     int64_t cap, partial_slots;
     int lane_recs, target;
-    int eval_grid[nb::kClasses], finish_grid;
+    int eval_grid, finish_grid;
     char msg[512];
     // host job table
     std::vector<int64_t> off, n, tend;
@@ -1055,8 +1086,9 @@ struct nb_batch {
     nb::Status *h_status;
     bool jobs_dirty;    // the job list changed since it was last uploaded
     int njobs;
-    hipGraph_t graph;   // one captured batch step (multi-step calls)
-    hipGraphExec_t gexec;
+    // captured batch steps for multi-step calls: [0] one step, [1] kGraphSteps steps
+    hipGraph_t graph[2];
+    hipGraphExec_t gexec[2];
     bool graph_valid, no_graph;
     int64_t *h_nact() { return reinterpret_cast<int64_t *>(h_jobblk); }
     int64_t *h_tnext() { return reinterpret_cast<int64_t *>(h_jobblk) + p.max_jobs; }
@@ -1193,18 +1225,10 @@ nb_status b_eval_finish(nb_batch *b, const int32_t *list, int n_list, int mode, 
                        b->target, wide_min, count);
     if (split) {
         const float e2 = (float)(b->p.eps * b->p.eps);
-        hipLaunchKernelGGL(nb::k_beval_split<nb::kClassTile>, dim3(b->eval_grid[nb::kClassTile]), dim3(64), 0,
-                           b->st, b->P, e2);
-        hipLaunchKernelGGL(nb::k_beval_split<nb::kClassDirect>, dim3(b->eval_grid[nb::kClassDirect]), dim3(64),
-                           0, b->st, b->P, e2);
+        hipLaunchKernelGGL(nb::k_beval_split, dim3(b->eval_grid), dim3(64), 0, b->st, b->P, e2);
     } else {
         const double e2 = b->p.eps * b->p.eps;
-        hipLaunchKernelGGL(nb::k_beval_f64<nb::kClassWide>, dim3(b->eval_grid[nb::kClassWide]), dim3(64), 0,
-                           b->st, b->P, e2);
-        hipLaunchKernelGGL(nb::k_beval_f64<nb::kClassTile>, dim3(b->eval_grid[nb::kClassTile]), dim3(64), 0,
-                           b->st, b->P, e2);
-        hipLaunchKernelGGL(nb::k_beval_f64<nb::kClassDirect>, dim3(b->eval_grid[nb::kClassDirect]), dim3(64),
-                           0, b->st, b->P, e2);
+        hipLaunchKernelGGL(nb::k_beval_f64, dim3(b->eval_grid), dim3(64), 0, b->st, b->P, e2);
     }
     hipLaunchKernelGGL(nb::k_bfinish, dim3(b->finish_grid), dim3(256), 0, b->st, b->P, b->cap, mode,
                        ldexp(1.0, b->p.dt_min_log2), b->p.eta, b->p.eta_init, b->p.dt_max_log2, L);
@@ -1251,42 +1275,52 @@ nb_status b_enqueue_step(nb_batch *b)
 
 void b_drop_graph(nb_batch *b)
 {
-    if (b->gexec)
-        (void)hipGraphExecDestroy(b->gexec);
-    if (b->graph)
-        (void)hipGraphDestroy(b->graph);
-    b->gexec = nullptr;
-    b->graph = nullptr;
+    for (int k = 0; k < 2; ++k) {
+        if (b->gexec[k])
+            (void)hipGraphExecDestroy(b->gexec[k]);
+        if (b->graph[k])
+            (void)hipGraphDestroy(b->graph[k]);
+        b->gexec[k] = nullptr;
+        b->graph[k] = nullptr;
+    }
     b->graph_valid = false;
 }
 
-// Capture one batch step's launches as a graph, replayed by multi-step calls (the
-// launches carry no per-step arguments: every size comes from device memory). No
-// memset or copy is captured. Returns false (and the caller launches directly) when
-// the stream cannot be captured, e.g. the null stream.
+// Steps per replay of the larger graph: back-to-back replays of one graph leave a
+// gap of about 13 us between them, the launches inside one graph a few us.
+constexpr int kGraphSteps = 8;
+
+// Capture batch steps as graphs, replayed by multi-step calls: one step and
+// kGraphSteps steps (the launches carry no per-step arguments: every size comes from
+// device memory). No memset or copy is captured. Returns false (and the caller
+// launches directly) when the stream cannot be captured, e.g. the null stream.
 bool b_capture_step(nb_batch *b)
 {
     b_drop_graph(b);
     if (!b->st || b->no_graph)
         return false;
-    if (hipStreamBeginCapture(b->st, hipStreamCaptureModeThreadLocal) != hipSuccess) {
-        (void)hipGetLastError();
-        b->no_graph = true;
-        return false;
+    for (int k = 0; k < 2; ++k) {
+        if (hipStreamBeginCapture(b->st, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+            (void)hipGetLastError();
+            b_drop_graph(b);
+            b->no_graph = true;
+            return false;
+        }
+        nb_status s = NB_OK;
+        for (int r = 0; r < (k ? kGraphSteps : 1) && s == NB_OK; ++r)
+            s = b_launch_step(b);
+        hipGraph_t g = nullptr;
+        const hipError_t e = hipStreamEndCapture(b->st, &g);
+        b->graph[k] = g;
+        if (s != NB_OK || e != hipSuccess || !g ||
+            hipGraphInstantiate(&b->gexec[k], g, nullptr, nullptr, 0) != hipSuccess) {
+            b->gexec[k] = nullptr;
+            (void)hipGetLastError();
+            b_drop_graph(b);
+            b->no_graph = true;
+            return false;
+        }
     }
-    const nb_status s = b_launch_step(b);
-    hipGraph_t g = nullptr;
-    const hipError_t e = hipStreamEndCapture(b->st, &g);
-    if (s != NB_OK || e != hipSuccess || !g ||
-        hipGraphInstantiate(&b->gexec, g, nullptr, nullptr, 0) != hipSuccess) {
-        if (g)
-            (void)hipGraphDestroy(g);
-        b->gexec = nullptr;
-        (void)hipGetLastError();
-        b->no_graph = true;
-        return false;
-    }
-    b->graph = g;
     b->graph_valid = true;
     return true;
 }
@@ -1357,27 +1391,14 @@ nb_status nb_batch_create(const nb_batch_params *p, void *d_workspace, size_t by
     b->free_ranges.push_back({0, p->capacity});
     b->jobs_dirty = true;
     // persistent evaluation: as many waves as can be resident on the device
-    int dev = 0, cus = 0, per[nb::kClasses] = {0, 0, 0}, fin = 0;
+    int dev = 0, cus = 0, per = 0, fin = 0;
     const bool sp = p->precision == NB_SPLIT;
     bool ok = hipGetDevice(&dev) == hipSuccess &&
               hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
-              hipOccupancyMaxActiveBlocksPerMultiprocessor(&fin, nb::k_bfinish, 256, 0) == hipSuccess;
-    if (sp)
-        ok = ok &&
-             hipOccupancyMaxActiveBlocksPerMultiprocessor(&per[nb::kClassTile],
-                                                          nb::k_beval_split<nb::kClassTile>, 64, 0) == hipSuccess &&
-             hipOccupancyMaxActiveBlocksPerMultiprocessor(&per[nb::kClassDirect],
-                                                          nb::k_beval_split<nb::kClassDirect>, 64, 0) == hipSuccess;
-    else
-        ok = ok &&
-             hipOccupancyMaxActiveBlocksPerMultiprocessor(&per[nb::kClassTile],
-                                                          nb::k_beval_f64<nb::kClassTile>, 64, 0) == hipSuccess &&
-             hipOccupancyMaxActiveBlocksPerMultiprocessor(&per[nb::kClassWide],
-                                                          nb::k_beval_f64<nb::kClassWide>, 64, 0) == hipSuccess &&
-             hipOccupancyMaxActiveBlocksPerMultiprocessor(&per[nb::kClassDirect],
-                                                          nb::k_beval_f64<nb::kClassDirect>, 64, 0) == hipSuccess;
-    for (int k = 0; k < nb::kClasses; ++k)
-        b->eval_grid[k] = std::max(1, cus * std::max(1, per[k]));
+              hipOccupancyMaxActiveBlocksPerMultiprocessor(&fin, nb::k_bfinish, 256, 0) == hipSuccess &&
+              (sp ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, nb::k_beval_split, 64, 0)
+                  : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, nb::k_beval_f64, 64, 0)) == hipSuccess;
+    b->eval_grid = std::max(1, cus * std::max(1, per));
     b->finish_grid = std::max(1, cus * std::max(1, fin));
     ok = ok && hipHostMalloc((void **)&b->h_scalar, 64, 0) == hipSuccess &&
          hipHostMalloc((void **)&b->h_jobblk, 20 * J, 0) == hipSuccess &&
@@ -1543,8 +1564,10 @@ nb_status nb_batch_run(nb_batch *b, int32_t steps, int64_t *h_n_act, int64_t *h_
     if ((s = b_upload_jobs(b)))
         return s;
     if (b->njobs > 0 && steps > 1 && (b->graph_valid || b_capture_step(b))) {
-        for (int k = 0; k < steps; ++k)
-            B_HIP(b, hipGraphLaunch(b->gexec, b->st));
+        for (int k = 0; k < steps / kGraphSteps; ++k)
+            B_HIP(b, hipGraphLaunch(b->gexec[1], b->st));
+        for (int k = 0; k < steps % kGraphSteps; ++k)
+            B_HIP(b, hipGraphLaunch(b->gexec[0], b->st));
     } else {
         for (int k = 0; k < steps; ++k)
             if ((s = b_launch_step(b)))
