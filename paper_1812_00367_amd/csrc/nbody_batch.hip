@@ -1,13 +1,13 @@
 // nbody_batch.hip -- many independent N-body systems ("jobs") of uneven size in one
 // workspace, advanced together: every batch step gives each job its own next block
 // step (its own block time and active set, the block-step scheme of the paper's
-// section "Code implementation"), with a fixed sequence of five launches for all jobs
+// section "Code implementation"), with a fixed sequence of four launches for all jobs
 // and no host work in between:
 //
 //   k_bact     one workgroup per job: next block time, active list (ascending);
-//   k_bpredict every body of every stepping job to its job's block time;
-//   k_plan     one workgroup: each stepping job's work split and the prefix sums that
-//              place its work items, partial sums and active bodies;
+//   k_bpredict_plan  every body of every stepping job to its job's block time, and in
+//              one more workgroup the plan: each stepping job's work split and the
+//              prefix sums that place its work items, partial sums and active bodies;
 //   k_beval    persistent waves taking work items (job, i-tile, j-chunk) until none
 //              is left, class after class (three item classes in FP64, two in split);
 //   k_bfinish  four lanes per active body: fixed-order sum of its partials,
@@ -246,14 +246,15 @@ __host__ __device__ inline bool tail_direct(int64_t na, int64_t tiles)
     return item_lanes(na - (tiles - 1) * kItemTile) >= kDirectW;
 }
 
-// Block-wide exclusive scans of NV 64-bit values at once (kBS threads): v[k] is
+// Block-wide exclusive scans of NV 64-bit values at once (NW waves): v[k] is
 // replaced by its exclusive prefix and tot[k] receives the block total. Each wave
-// scans its lanes, wave 0 scans the kBW wave totals into pre, and every thread adds
+// scans its lanes, wave 0 scans the NW wave totals into pre, and every thread adds
 // its wave's prefix: three barriers in all.
-template <int NV>
+template <int NV, int NW>
 __device__ __forceinline__ void block_scan(int64_t (&v)[NV], int64_t (&tot)[NV], int64_t (*scr)[NV],
                                            int64_t (*pre)[NV])
 {
+    static_assert(NW <= 32, "wave totals are scanned by one wave");
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     int64_t inc[NV];
 #pragma unroll
@@ -272,17 +273,17 @@ __device__ __forceinline__ void block_scan(int64_t (&v)[NV], int64_t (&tot)[NV],
             scr[wave][k] = inc[k];
     __syncthreads();
     if (wave == 0) {
-        // lane w <= kBW: sum of the totals of waves before w (lane kBW: all of them)
+        // lane w <= NW: sum of the totals of waves before w (lane NW: all of them)
 #pragma unroll
         for (int k = 0; k < NV; ++k) {
-            int64_t x = lane < kBW ? scr[lane][k] : 0;
+            int64_t x = lane < NW ? scr[lane][k] : 0;
             for (int o = 1; o < 32; o <<= 1) {
                 const int64_t u = __shfl_up(x, o, 64);
                 if (lane >= o)
                     x += u;
             }
             const int64_t ex = __shfl_up(x, 1, 64);
-            if (lane <= kBW)
+            if (lane <= NW)
                 pre[lane][k] = lane == 0 ? 0 : ex;
         }
     }
@@ -290,17 +291,21 @@ __device__ __forceinline__ void block_scan(int64_t (&v)[NV], int64_t (&tot)[NV],
 #pragma unroll
     for (int k = 0; k < NV; ++k) {
         v[k] = pre[wave][k] + inc[k] - v[k];
-        tot[k] = pre[kBW][k];
+        tot[k] = pre[NW][k];
     }
     __syncthreads();
 }
 
-__global__ __launch_bounds__(kBS) void k_plan(Pool P, const int32_t *__restrict__ jobs, int njobs,
-                                              int lane_recs, int target, int64_t wide_min, int count)
+// The step's plan over the listed jobs, by one workgroup of kPlanBS threads.
+constexpr int kPlanBS = 256;
+
+__device__ __forceinline__ void plan_jobs(const Pool &P, const int32_t *__restrict__ jobs, int njobs,
+                                          int lane_recs, int target, int64_t wide_min, int count)
 {
-    __shared__ int64_t scr[kBW][7], pre[kBW + 1][7];
+    constexpr int NW = kPlanBS / 64;
+    __shared__ int64_t scr[NW][7], pre[NW + 1][7];
     int64_t c_plan = 0, c_it[kClasses] = {0, 0, 0}, c_act = 0, c_ps = 0, c_inter = 0;
-    for (int base = 0; base < njobs; base += kBS) {
+    for (int base = 0; base < njobs; base += kPlanBS) {
         const int p = base + (int)threadIdx.x;
         int job = -1;
         int64_t na = 0, n = 0;
@@ -321,7 +326,7 @@ __global__ __launch_bounds__(kBS) void k_plan(Pool P, const int32_t *__restrict_
         // exclusive prefixes and totals of: stepping jobs, items of each class, active
         // bodies, partial-sum slots, interactions
         int64_t x[7] = {on ? 1 : 0, n_items[0], n_items[1], n_items[2], na, sp.S * na, na * n}, t[7];
-        block_scan<7>(x, t, scr, pre);
+        block_scan<7, NW>(x, t, scr, pre);
         const int64_t x_plan = x[0], x_it[kClasses] = {x[1], x[2], x[3]}, x_act = x[4], x_ps = x[5];
         const int64_t t_plan = t[0], t_it[kClasses] = {t[1], t[2], t[3]}, t_act = t[4], t_ps = t[5],
                       t_int = t[6];
@@ -363,6 +368,12 @@ __global__ __launch_bounds__(kBS) void k_plan(Pool P, const int32_t *__restrict_
     }
 }
 
+__global__ __launch_bounds__(kPlanBS) void k_plan(Pool P, const int32_t *__restrict__ jobs, int njobs,
+                                                  int lane_recs, int target, int64_t wide_min, int count)
+{
+    plan_jobs(P, jobs, njobs, lane_recs, target, wide_min, count);
+}
+
 // Largest k in [0, count) with prefix[k] <= e (prefix ascending, prefix[0] = 0).
 template <typename T>
 __device__ __forceinline__ int find_entry(const T *__restrict__ prefix, int count, int64_t e)
@@ -394,10 +405,17 @@ __device__ __forceinline__ const int64_t *cache_prefix(const int64_t *__restrict
 }
 
 // --------------------------------------------------------------- prediction ----
-// Every body of a job that steps (n_act > 0) to its job's block time.
-__global__ __launch_bounds__(256) void k_bpredict(Pool P, int64_t cap, double tick_size, int split)
+// Workgroup 0 builds the step's plan (it needs only the active counts); the others
+// predict every body of a job that steps (n_act > 0) to its job's block time.
+__global__ __launch_bounds__(kPlanBS) void k_bpredict_plan(Pool P, int64_t cap, double tick_size, int split,
+                                                           const int32_t *__restrict__ jobs, int njobs,
+                                                           int lane_recs, int target, int64_t wide_min)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (blockIdx.x == 0) {
+        plan_jobs(P, jobs, njobs, lane_recs, target, wide_min, 1);
+        return;
+    }
+    const int64_t i = (int64_t)(blockIdx.x - 1) * kPlanBS + threadIdx.x;
     if (i >= cap)
         return;
     const int job = P.body_job[i];
@@ -1213,16 +1231,19 @@ const char *b_check_params(const nb_batch_params *p)
     return nullptr;
 }
 
+// The wide class (two bodies per lane) is FP64 only.
+int64_t b_wide_min(const nb_batch *b) { return b->p.precision == NB_SPLIT ? INT64_MAX : nb::kWideMin; }
+
 // Launches of one evaluation over the jobs in `list` (n_list entries, device array)
 // whose n_act is in j_nact, then the finishing pass in `mode`. No host work between.
-nb_status b_eval_finish(nb_batch *b, const int32_t *list, int n_list, int mode, int count)
+// planned: the plan of this evaluation is already built.
+nb_status b_eval_finish(nb_batch *b, const int32_t *list, int n_list, int mode, int count, bool planned = false)
 {
     const bool split = b->p.precision == NB_SPLIT;
     const int L = b->p.dt_max_log2 - b->p.dt_min_log2;
-    // the wide class (two bodies per lane) is FP64 only
-    const int64_t wide_min = split ? INT64_MAX : nb::kWideMin;
-    hipLaunchKernelGGL(nb::k_plan, dim3(1), dim3(nb::kBS), 0, b->st, b->P, list, n_list, b->lane_recs,
-                       b->target, wide_min, count);
+    if (!planned)
+        hipLaunchKernelGGL(nb::k_plan, dim3(1), dim3(nb::kPlanBS), 0, b->st, b->P, list, n_list, b->lane_recs,
+                           b->target, b_wide_min(b), count);
     if (split) {
         const float e2 = (float)(b->p.eps * b->p.eps);
         hipLaunchKernelGGL(nb::k_beval_split, dim3(b->eval_grid), dim3(64), 0, b->st, b->P, e2);
@@ -1261,10 +1282,11 @@ nb_status b_launch_step(nb_batch *b)
     const bool split = b->p.precision == NB_SPLIT;
     hipLaunchKernelGGL(nb::k_bact, dim3(b->njobs), dim3(nb::kBS), 0, b->st, b->P, (const int32_t *)b->d_jobs,
                        b->p.dt_max_log2 - b->p.dt_min_log2);
-    hipLaunchKernelGGL(nb::k_bpredict, dim3(nb::nblk(b->cap, 256)), dim3(256), 0, b->st, b->P, b->cap,
-                       ldexp(1.0, b->p.dt_min_log2), (int)split);
+    hipLaunchKernelGGL(nb::k_bpredict_plan, dim3(1 + nb::nblk(b->cap, nb::kPlanBS)), dim3(nb::kPlanBS), 0, b->st,
+                       b->P, b->cap, ldexp(1.0, b->p.dt_min_log2), (int)split, (const int32_t *)b->d_jobs,
+                       b->njobs, b->lane_recs, b->target, b_wide_min(b));
     B_HIP(b, hipGetLastError());
-    return b_eval_finish(b, b->d_jobs, b->njobs, nb::kStep, 1);
+    return b_eval_finish(b, b->d_jobs, b->njobs, nb::kStep, 1, true);
 }
 
 nb_status b_enqueue_step(nb_batch *b)
