@@ -627,10 +627,11 @@ __device__ __forceinline__ void sweep_lds_f64(const double2 *__restrict__ src, i
     }
 }
 
-// Work items are taken persistently. In a class claimed statically, wave b takes
-// item b first and further items come from the class's counter numbered from the
-// grid size on (the first round needs no atomic); in a class claimed dynamically
-// every item comes from the counter, so a wave still busy elsewhere holds none back.
+// Work items are taken persistently, the classes of a launch in a fixed order. The
+// first round is static: wave b takes item b of the classes' items laid end to end
+// (so no wave waits on an atomic to start, and none is held back); a class with more
+// items than the waves left for it hands the rest out from its counter, to waves that
+// have finished their static item or the earlier classes.
 __device__ __forceinline__ int64_t claim_item(const Pool &P, int cls, int64_t base)
 {
     unsigned int got = 0;
@@ -639,16 +640,29 @@ __device__ __forceinline__ int64_t claim_item(const Pool &P, int cls, int64_t ba
     return base + (int64_t)__shfl(got, 0, 64);
 }
 
-// The items of one class (first: claimed statically).
+// First item of this wave in a class whose items start at position `before` of the
+// launch's static round (nstat of them are static); -1 when the wave has none there.
+__device__ __forceinline__ int64_t first_item(const Pool &P, int cls, int64_t nitems, int64_t before,
+                                              int64_t *nstat)
+{
+    const int64_t G = gridDim.x, b = blockIdx.x;
+    const int64_t room = G > before ? G - before : 0;
+    *nstat = nitems < room ? nitems : room;
+    if (b >= before && b - before < *nstat)
+        return b - before;
+    return *nstat < nitems ? claim_item(P, cls, *nstat) : -1;
+}
+
+// The items of one class; `before` = the items of the classes ahead of it.
 template <int CLS>
 __device__ __forceinline__ void eval_items_f64(const Pool &P, double eps2, double2 (*lds)[kItemTile * 5],
-                                               int64_t *s_item0, bool first)
+                                               int64_t *s_item0, int64_t before)
 {
     const int64_t nitems = P.hdr->nitems[CLS];
     const int nplan = P.hdr->nplan;
-    const int64_t base = first ? (int64_t)gridDim.x : 0;
-    int64_t item = first ? (int64_t)blockIdx.x : (nitems > 0 ? claim_item(P, CLS, 0) : 0);
-    if (item >= nitems)  // the other waves drain every item
+    int64_t base;
+    int64_t item = first_item(P, CLS, nitems, before, &base);
+    if (item < 0 || item >= nitems)  // the other waves drain every item
         return;
     __syncthreads();  // the previous class is done with s_item0
     const int64_t *item0 = cache_prefix(P.pl_item0[CLS], nplan, s_item0);
@@ -697,23 +711,22 @@ __device__ __forceinline__ void eval_items_f64(const Pool &P, double eps2, doubl
                               reinterpret_cast<double2 (*)[kItemTile * 5]>(&lds[0][0]));
             finish_item(P, b, it, bad);
         }
-        item = claim_item(P, CLS, base);
+        item = base < nitems ? claim_item(P, CLS, base) : nitems;
     }
 }
 
 // All FP64 items of a step in one launch, class after class, so a wave that runs out
 // of one class moves on while others finish theirs: first the direct class (few
 // items, bound by load latency, which then overlaps the arithmetic of the others),
-// then the wide class (the longest items), both claimed statically, then the tile
-// class, claimed dynamically as waves come free (statically when it is alone).
+// then the wide class (the longest items), then the tile class.
 __global__ __launch_bounds__(64) void k_beval_f64(Pool P, double eps2)
 {
     __shared__ double2 lds[2][kItemTile * 5];
     __shared__ int64_t s_item0[kPlanCache];
-    const bool tile_alone = P.hdr->nitems[kClassDirect] == 0 && P.hdr->nitems[kClassWide] == 0;
-    eval_items_f64<kClassDirect>(P, eps2, lds, s_item0, true);
-    eval_items_f64<kClassWide>(P, eps2, lds, s_item0, true);
-    eval_items_f64<kClassTile>(P, eps2, lds, s_item0, tile_alone);
+    const int64_t nd = P.hdr->nitems[kClassDirect], nw = P.hdr->nitems[kClassWide];
+    eval_items_f64<kClassDirect>(P, eps2, lds, s_item0, 0);
+    eval_items_f64<kClassWide>(P, eps2, lds, s_item0, nd);
+    eval_items_f64<kClassTile>(P, eps2, lds, s_item0, nd + nw);
 }
 
 // ------------------------------------------------------ split-precision path ----
@@ -830,16 +843,16 @@ __device__ __forceinline__ void sweep_lds_split(const float4 *__restrict__ src, 
 
 template <int CLS>
 __device__ __forceinline__ void eval_items_split(const Pool &P, float eps2, float4 (*lds)[kItemTile * 4],
-                                                 int64_t *s_item0, bool first)
+                                                 int64_t *s_item0, int64_t before)
 {
     static_assert(CLS != kClassWide, "the split path has no wide class");
     constexpr bool DIRECT = CLS == kClassDirect;
     constexpr int cls = CLS;
     const int64_t nitems = P.hdr->nitems[cls];
     const int nplan = P.hdr->nplan;
-    const int64_t base = first ? (int64_t)gridDim.x : 0;
-    int64_t item = first ? (int64_t)blockIdx.x : (nitems > 0 ? claim_item(P, cls, 0) : 0);
-    if (item >= nitems)  // the other waves drain every item
+    int64_t base;
+    int64_t item = first_item(P, cls, nitems, before, &base);
+    if (item < 0 || item >= nitems)  // the other waves drain every item
         return;
     __syncthreads();  // the previous class is done with s_item0
     const int64_t *item0 = cache_prefix(P.pl_item0[cls], nplan, s_item0);
@@ -870,7 +883,7 @@ __device__ __forceinline__ void eval_items_split(const Pool &P, float eps2, floa
             sweep_lds_split(src, it.jbeg, it.jend, it.W, it.lw, it.w, b, lo, hi, eps2,
                             reinterpret_cast<float4 (*)[kItemTile * 4]>(&lds[0][0]));
         finish_item(P, b, it, bad);
-        item = claim_item(P, cls, base);
+        item = base < nitems ? claim_item(P, cls, base) : nitems;
     }
 }
 
@@ -880,8 +893,8 @@ __global__ __launch_bounds__(64) void k_beval_split(Pool P, float eps2)
 {
     __shared__ float4 lds[2][kItemTile * 4];
     __shared__ int64_t s_item0[kPlanCache];
-    eval_items_split<kClassDirect>(P, eps2, lds, s_item0, true);
-    eval_items_split<kClassTile>(P, eps2, lds, s_item0, P.hdr->nitems[kClassDirect] == 0);
+    eval_items_split<kClassDirect>(P, eps2, lds, s_item0, 0);
+    eval_items_split<kClassTile>(P, eps2, lds, s_item0, P.hdr->nitems[kClassDirect]);
 }
 
 // ------------------------------------------------- per active body: finishing ----
