@@ -66,7 +66,7 @@ struct Pool {
     double *m, *x, *v, *a, *j, *s, *c, *a4n, *a5n, *phi;
     int64_t *tick;
     int32_t *level;
-    int32_t *body_job;  // job id of every pool slot, -1 when free
+    int2 *pblk;         // prediction blocks of the listed jobs: {job, first body} per kPlanBS bodies
     double *jrec;
     float *jrec32;
     int32_t *act;       // job j's active list (pool indices) at off_j
@@ -406,7 +406,9 @@ __device__ __forceinline__ const int64_t *cache_prefix(const int64_t *__restrict
 
 // --------------------------------------------------------------- prediction ----
 // Workgroup 0 builds the step's plan (it needs only the active counts); the others
-// predict every body of a job that steps (n_act > 0) to its job's block time.
+// predict every body of a job that steps (n_act > 0) to its job's block time, one
+// workgroup per kPlanBS bodies of each listed job (a table the host builds when the
+// job list changes, so a step touches only the jobs' bodies, not the whole pool).
 __global__ __launch_bounds__(kPlanBS) void k_bpredict_plan(Pool P, int64_t cap, double tick_size, int split,
                                                            const int32_t *__restrict__ jobs, int njobs,
                                                            int lane_recs, int target, int64_t wide_min)
@@ -415,12 +417,12 @@ __global__ __launch_bounds__(kPlanBS) void k_bpredict_plan(Pool P, int64_t cap, 
         plan_jobs(P, jobs, njobs, lane_recs, target, wide_min, 1);
         return;
     }
-    const int64_t i = (int64_t)(blockIdx.x - 1) * kPlanBS + threadIdx.x;
-    if (i >= cap)
+    const int2 blk = P.pblk[blockIdx.x - 1];
+    const int job = blk.x;
+    const int64_t k = (int64_t)blk.y + threadIdx.x;
+    if (k >= P.j_n[job] || P.j_nact[job] == 0)
         return;
-    const int job = P.body_job[i];
-    if (job < 0 || P.j_nact[job] == 0)
-        return;
+    const int64_t i = P.j_off[job] + k;
     const int64_t tn = P.j_tnext[job], ti = P.tick[i];
     if (ti > tn) {
         P.j_err[job] = kJobLevel;
@@ -1006,10 +1008,8 @@ __global__ __launch_bounds__(256) void k_bjob_init(Pool P, int job, int64_t off,
         P.j_tnext[job] = tick0;
         P.j_err[job] = kJobOk;
     }
-    if (k < n) {
+    if (k < n)
         P.act[off + k] = (int32_t)(off + k);
-        P.body_job[off + k] = job;
-    }
 }
 
 // Load a job's state from caller arrays laid out [3][n] into the pool ([3][cap]).
@@ -1065,13 +1065,6 @@ __global__ __launch_bounds__(256) void k_bstore(Pool P, int64_t cap, int64_t off
     if (level) level[k] = P.level[i];
 }
 
-__global__ __launch_bounds__(256) void k_bfree(Pool P, int64_t off, int64_t n)
-{
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k < n)
-        P.body_job[off + k] = -1;
-}
-
 __global__ __launch_bounds__(64) void k_hdr_reset(Pool P)
 {
     if (threadIdx.x == 0) {
@@ -1114,6 +1107,8 @@ struct nb_batch {
     nb::StepHdr *h_hdr;
     int32_t *h_jobs;
     int32_t *d_jobs, *d_one;
+    int2 *h_pblk;       // prediction blocks of the listed jobs (host copy)
+    int64_t npblk;
     nb::Status *h_status;
     bool jobs_dirty;    // the job list changed since it was last uploaded
     int njobs;
@@ -1151,6 +1146,10 @@ int64_t b_partial_slots(const nb_batch_params *p)
 }
 
 // device workspace layout; returns bytes (base may be null to measure)
+// Entries of the prediction-block table: one per kPlanBS bodies of each job, at most
+// capacity / kPlanBS + max_jobs.
+int64_t b_pblk_max(const nb_batch_params *p) { return p->capacity / nb::kPlanBS + p->max_jobs + 1; }
+
 size_t b_layout(const nb_batch_params *p, Pool *P, int32_t **d_jobs, int32_t **d_one, char *base)
 {
     const size_t cap = (size_t)p->capacity, J = (size_t)p->max_jobs;
@@ -1175,7 +1174,7 @@ size_t b_layout(const nb_batch_params *p, Pool *P, int32_t **d_jobs, int32_t **d
     P->phi = (double *)take(8 * cap);
     P->tick = (int64_t *)take(8 * cap);
     P->level = (int32_t *)take(4 * cap);
-    P->body_job = (int32_t *)take(4 * cap);
+    P->pblk = (int2 *)take(8 * (size_t)b_pblk_max(p));
     P->jrec = (double *)take(8 * nb::kRecD * cap);
     P->jrec32 = split ? (float *)take(4 * nb::kRecF * cap) : nullptr;
     P->act = (int32_t *)take(4 * cap);
@@ -1276,11 +1275,17 @@ nb_status b_upload_jobs(nb_batch *b)
 {
     if (b->jobs_dirty) {
         b->njobs = 0;
+        b->npblk = 0;
         for (int k = 0; k < b->p.max_jobs; ++k)
-            if (b->alive[k])
+            if (b->alive[k]) {
                 b->h_jobs[b->njobs++] = k;
-        if (b->njobs > 0)
+                for (int64_t base = 0; base < b->n[k]; base += nb::kPlanBS)
+                    b->h_pblk[b->npblk++] = make_int2(k, (int)base);
+            }
+        if (b->njobs > 0) {
             B_HIP(b, hipMemcpyAsync(b->d_jobs, b->h_jobs, 4 * (size_t)b->njobs, hipMemcpyHostToDevice, b->st));
+            B_HIP(b, hipMemcpyAsync(b->P.pblk, b->h_pblk, 8 * (size_t)b->npblk, hipMemcpyHostToDevice, b->st));
+        }
         b->jobs_dirty = false;
         b->graph_valid = false;  // the captured step launches a grid per listed job
     }
@@ -1295,7 +1300,7 @@ nb_status b_launch_step(nb_batch *b)
     const bool split = b->p.precision == NB_SPLIT;
     hipLaunchKernelGGL(nb::k_bact, dim3(b->njobs), dim3(nb::kBS), 0, b->st, b->P, (const int32_t *)b->d_jobs,
                        b->p.dt_max_log2 - b->p.dt_min_log2);
-    hipLaunchKernelGGL(nb::k_bpredict_plan, dim3(1 + nb::nblk(b->cap, nb::kPlanBS)), dim3(nb::kPlanBS), 0, b->st,
+    hipLaunchKernelGGL(nb::k_bpredict_plan, dim3(1 + b->npblk), dim3(nb::kPlanBS), 0, b->st,
                        b->P, b->cap, ldexp(1.0, b->p.dt_min_log2), (int)split, (const int32_t *)b->d_jobs,
                        b->njobs, b->lane_recs, b->target, b_wide_min(b));
     B_HIP(b, hipGetLastError());
@@ -1439,11 +1444,11 @@ nb_status nb_batch_create(const nb_batch_params *p, void *d_workspace, size_t by
          hipHostMalloc((void **)&b->h_jobblk, 20 * J, 0) == hipSuccess &&
          hipHostMalloc((void **)&b->h_hdr, sizeof(nb::StepHdr), 0) == hipSuccess &&
          hipHostMalloc((void **)&b->h_jobs, 4 * J, 0) == hipSuccess &&
+         hipHostMalloc((void **)&b->h_pblk, 8 * (size_t)b_pblk_max(p), 0) == hipSuccess &&
          hipHostMalloc((void **)&b->h_status, sizeof(nb::Status), 0) == hipSuccess;
     if (ok) {
         hipLaunchKernelGGL(nb::k_hdr_reset, dim3(1), dim3(64), 0, b->st, b->P);
         ok = hipGetLastError() == hipSuccess &&
-             nb::launch_fill_i32(b->P.body_job, -1, (size_t)b->cap, b->st) == hipSuccess &&
              nb::launch_fill_i32(b->P.j_err, 0, J, b->st) == hipSuccess &&
              nb::launch_fill_i64(b->P.j_nact, 0, J, b->st) == hipSuccess &&
              nb::launch_fill_i32((int32_t *)b->P.status, 0, sizeof(nb::Status) / 4, b->st) == hipSuccess &&
@@ -1464,7 +1469,7 @@ void nb_batch_destroy(nb_batch *b)
     (void)hipStreamSynchronize(b->st);
     b_drop_graph(b);
     for (void *q : {(void *)b->h_scalar, (void *)b->h_jobblk, (void *)b->h_hdr, (void *)b->h_jobs,
-                    (void *)b->h_status})
+                    (void *)b->h_pblk, (void *)b->h_status})
         if (q)
             (void)hipHostFree(q);
     delete b;
@@ -1526,7 +1531,6 @@ nb_status nb_batch_add(nb_batch *b, int64_t n, const nb_state *src, int64_t tick
         s = b_fetch(b);
     if (s) {
         // leave the range and the job slot unclaimed, so no later step touches them
-        hipLaunchKernelGGL(nb::k_bfree, dim3(nb::nblk(n, 256)), dim3(256), 0, b->st, b->P, off, n);
         (void)nb::launch_fill_i64(b->P.j_nact + job, 0, 1, b->st);
         (void)hipStreamSynchronize(b->st);
         return s;
@@ -1549,8 +1553,6 @@ nb_status nb_batch_remove(nb_batch *b, int32_t job)
     if (job < 0 || job >= b->p.max_jobs || !b->alive[job])
         return bfail(b, NB_ERR_ARG, "job %d is not in the batch", job);
     b->jobs_dirty = true;
-    hipLaunchKernelGGL(nb::k_bfree, dim3(nb::nblk(b->n[job], 256)), dim3(256), 0, b->st, b->P, b->off[job],
-                       b->n[job]);
     B_HIP(b, nb::launch_fill_i64(b->P.j_nact + job, 0, 1, b->st));
     B_HIP(b, hipGetLastError());
     B_HIP(b, hipStreamSynchronize(b->st));
