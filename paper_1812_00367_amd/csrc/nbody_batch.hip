@@ -90,12 +90,12 @@ struct Pool {
 // tick_next is beyond the job's end time or the job has failed.
 constexpr int kBS = 1024;
 constexpr int kBW = kBS / 64;
-constexpr int kUnroll = 4;
+constexpr int kUnroll = 8;  // bodies per thread per round of the active-set scans
 
 __global__ __launch_bounds__(kBS) void k_bact(Pool P, const int32_t *__restrict__ jobs, int L)
 {
     __shared__ int64_t red[kBW];
-    __shared__ int wc[kBW];
+    __shared__ int wcu[kUnroll][kBW];
     __shared__ int sbad[kBW];
     const int job = jobs[blockIdx.x];
     // a failed job, or one whose last block time reached its end (every body is then
@@ -149,26 +149,40 @@ __global__ __launch_bounds__(kBS) void k_bact(Pool P, const int32_t *__restrict_
     const bool skip = tn > P.j_tend[job] || err0 != kJobOk || anybad;
     int64_t base = 0;
     if (!skip) {
-        for (int64_t r0 = 0; r0 < n; r0 += kBS) {
-            const int64_t k = r0 + threadIdx.x;
-            bool due = false;
-            if (k < n) {
-                int lv = P.level[off + k];
+        // super-rounds of kUnroll chunks of kBS bodies: loads issued together, one
+        // barrier pair per super-round; chunk u of a super-round starts after the due
+        // bodies of chunks 0 .. u-1, and within a chunk the order is the thread order
+        for (int64_t r0 = 0; r0 < n; r0 += kUnroll * kBS) {
+            bool due[kUnroll];
+            unsigned long long mask[kUnroll];
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) {
+                const int64_t k = r0 + u * kBS + threadIdx.x;
+                int lv = k < n ? P.level[off + k] : 0;
+                const int64_t tk = k < n ? P.tick[off + k] : 0;
                 lv = (lv < 0 || lv > L) ? L : lv;
-                due = P.tick[off + k] + ((int64_t)1 << (L - lv)) == tn;
+                due[u] = k < n && tk + ((int64_t)1 << (L - lv)) == tn;
             }
-            const unsigned long long mask = __ballot(due);
-            if (lane == 0)
-                wc[wave] = __popcll(mask);
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) {
+                mask[u] = __ballot(due[u]);
+                if (lane == 0)
+                    wcu[u][wave] = __popcll(mask[u]);
+            }
             __syncthreads();
-            int before = 0, tot = 0;
-            for (int w = 0; w < kBW; ++w) {
-                before += (w < wave) ? wc[w] : 0;
-                tot += wc[w];
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) {
+                int before = 0, tot = 0;
+                for (int w = 0; w < kBW; ++w) {
+                    const int c = wcu[u][w];
+                    before += w < wave ? c : 0;
+                    tot += c;
+                }
+                if (due[u])
+                    P.act[off + base + before + __popcll(mask[u] & ((1ull << lane) - 1ull))] =
+                        (int32_t)(off + r0 + u * kBS + threadIdx.x);
+                base += tot;
             }
-            if (due)
-                P.act[off + base + before + __popcll(mask & ((1ull << lane) - 1ull))] = (int32_t)(off + k);
-            base += tot;
             __syncthreads();
         }
     }
