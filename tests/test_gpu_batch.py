@@ -314,3 +314,37 @@ def test_batch_split_startup_within_rounding_bound(nb):
         ref = oracle.evaluate(ic.m, ic.x, ic.v, st["a"], 1e-4)
         env = envelope(ic.m, ic.x, ic.v, st["a"], 1e-4, np.arange(n))
         check_split(got, ref, env, f"batch split n={n}")
+
+
+# ------------------------------------------ active sets of jobs over 8192 bodies --
+def test_batch_active_sets_of_large_jobs(nb):
+    """Jobs of 9000 and 17001 bodies (the active-set scan takes 8192 bodies per round:
+    two and three rounds, the last ragged) beside a small one: after every batch step
+    the bodies that advanced are exactly the oracle's active set computed from the
+    job's times and levels before the step, and the reported count and block time
+    match it."""
+    sizes = [9000, 300, 17001]
+    b = make_batch(nb, sum(sizes), 3)
+    jobs = []
+    for k, n in enumerate(sizes):
+        ic = cluster(n, 900 + k)
+        jobs.append(b.add(ic.m, ic.x, ic.v, 1 << L))
+    checked = {j: 0 for j in jobs}
+    for step in range(24):
+        before = {j: {k: host(t) for k, t in b.get(j).items() if k in ("tick", "level")} for j in jobs}
+        nact, tnext, err, _ = b.step()
+        for j in jobs:
+            assert err[j] == 0, (step, j, err[j])
+            idx, tn = oracle.active(before[j]["tick"], before[j]["level"], L)
+            after = host(b.get(j)["tick"])
+            if nact[j] == 0:
+                assert tn > (1 << L) or len(idx) == 0, (step, j)
+                assert np.array_equal(after, before[j]["tick"]), (step, j)
+                continue
+            assert tnext[j] == tn and nact[j] == len(idx), (step, j, tnext[j], tn, nact[j], len(idx))
+            moved = np.flatnonzero(after != before[j]["tick"]).astype(np.int32)
+            assert np.array_equal(moved, idx), (step, j)
+            assert np.all(after[idx] == tn), (step, j)
+            checked[j] += 1
+    say("large-job active sets checked per job:", checked)
+    assert all(v > 0 for v in checked.values())
