@@ -213,11 +213,14 @@ __host__ __device__ inline int item_lanes(int64_t rem)
 // Split of one job's evaluation: tiles = ceil(n_act / 64) i-tiles (of 128 for a wide
 // job, n_act >= wide_min), S j-chunks of jch bodies. S gives every lane about
 // `lane_recs` records (lane_recs 16 / W when W > 16 lanes share a body, so that a job
-// with one to three active bodies still spreads over several waves; kWideRecs x
-// lane_recs in a wide item, whose 128 bodies amortise a longer chunk and write a
-// quarter of the partial sums), but no more chunks than make `target` work items for
-// the job. Depends on (n, n_act) and the batch constants only.
+// with one to three active bodies still spreads over several waves), times kWideRecs
+// in a wide item and kTileRecs in a tile item with fewer than 8 lanes per body:
+// longer chunks there amortise each item's set-up and leave fewer partial sums for
+// the finishing pass to add (measured: 4 for wide items, 2 for tile items), but no
+// more chunks than make `target` work items for the job. Depends on (n, n_act) and
+// the batch constants only.
 constexpr int kWideRecs = 4;
+constexpr int kTileRecs = 2;
 
 struct JobSplit {
     int64_t tiles, S, jch;
@@ -232,7 +235,7 @@ __host__ __device__ inline JobSplit job_split(int64_t n, int64_t na, int lane_re
     const int64_t tw = r.wide ? 2 * kItemTile : kItemTile;
     r.tiles = (na + tw - 1) / tw;
     const int64_t W = r.wide ? 1 : item_lanes(na < 64 ? na : 64);
-    const int64_t per = (int64_t)lane_recs * (r.wide ? kWideRecs : (W < 16 ? W : 16));  // bodies per chunk
+    const int64_t per = (int64_t)lane_recs * (r.wide ? kWideRecs : W < 8 ? kTileRecs * W : (W < 16 ? W : 16));
     int64_t S = (n + per - 1) / per;
     const int64_t cap = (target + r.tiles - 1) / r.tiles;
     S = S < cap ? S : cap;
