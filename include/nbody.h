@@ -247,11 +247,17 @@ typedef struct {
     double eps, eta, eta_init;        /* as in nb_params, shared by every job */
     int32_t dt_max_log2, dt_min_log2; /* as in nb_params */
     int32_t jchunk;        /* j-records per lane of a work item (multiple of 64; 0 = 64):
-                              sets a job's j-chunks, S = ceil(n / (jchunk W)) where W lanes
-                              share an active body (W = 64 / next power of two >= n_act for
-                              n_act < 64, else 1) */
+                              sets a job's j-chunks, S = ceil(n / (jchunk f min(W, 16)))
+                              where W lanes share an active body (W = 64 / next power of two
+                              >= n_act for n_act < 64, else 1) and f is the factor of the
+                              job's item class below */
     int32_t items_per_job; /* at most this many work items per job and step come from
                               j-chunks (an upper bound on S i-tiles; 0 = 2048, <= 16384) */
+    int32_t chunk_tile;    /* factor f of a job with 9 <= n_act < 128 (tile items; and of a
+                              split-precision job with n_act >= 9): 0 = 2, <= 64 */
+    int32_t chunk_wide;    /* factor f of an FP64 job with n_act >= 128 (wide items, 128
+                              active bodies each): 0 = 4, <= 64 */
+    int32_t chunk_direct;  /* factor f of a job with n_act <= 8 (direct items): 0 = 1, <= 64 */
     int64_t partial_slots; /* partial-sum buffer in (j-chunk x active body) units; raised to
                               the bound every step fits, 2 capacity + 128 (items_per_job + 1)
                               max_jobs; 0 = that bound */

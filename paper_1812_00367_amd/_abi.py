@@ -58,6 +58,9 @@ class BatchParams(ctypes.Structure):
         ("dt_min_log2", ctypes.c_int32),
         ("jchunk", ctypes.c_int32),
         ("items_per_job", ctypes.c_int32),
+        ("chunk_tile", ctypes.c_int32),
+        ("chunk_wide", ctypes.c_int32),
+        ("chunk_direct", ctypes.c_int32),
         ("partial_slots", ctypes.c_int64),
         ("stream", ctypes.c_void_p),
     ]

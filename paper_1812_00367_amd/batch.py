@@ -23,11 +23,13 @@ def _ptr(t):
 
 def batch_workspace_bytes(capacity, max_jobs, precision=NB_FP64, eps=1e-4, eta=0.45,
                           eta_init=0.01, dt_max_log2=-3, dt_min_log2=-40, jchunk=0,
-                          items_per_job=0, partial_slots=0):
+                          items_per_job=0, partial_slots=0, chunk_tile=0, chunk_wide=0,
+                          chunk_direct=0):
     lib = _abi.load()
     p = _abi.BatchParams(capacity=capacity, max_jobs=max_jobs, precision=precision, eps=eps,
                          eta=eta, eta_init=eta_init, dt_max_log2=dt_max_log2,
                          dt_min_log2=dt_min_log2, jchunk=jchunk, items_per_job=items_per_job,
+                         chunk_tile=chunk_tile, chunk_wide=chunk_wide, chunk_direct=chunk_direct,
                          partial_slots=partial_slots, stream=None)
     out = ctypes.c_size_t(0)
     rc = lib.nb_batch_workspace_bytes(ctypes.byref(p), ctypes.byref(out))
@@ -37,11 +39,14 @@ def batch_workspace_bytes(capacity, max_jobs, precision=NB_FP64, eps=1e-4, eta=0
 
 
 class Batch:
-    """A pool of `capacity` bodies shared by at most `max_jobs` jobs on one GPU."""
+    """A pool of `capacity` bodies shared by at most `max_jobs` jobs on one GPU.
+
+    jchunk, items_per_job and chunk_tile / chunk_wide / chunk_direct set the work
+    split (the fields of nb_batch_params; 0 = the library defaults)."""
 
     def __init__(self, capacity, max_jobs, eps=1e-4, eta=0.45, eta_init=0.01, dt_max_log2=-3,
                  dt_min_log2=-40, precision=NB_FP64, jchunk=0, items_per_job=0, partial_slots=0,
-                 device=None, stream=None):
+                 device=None, stream=None, chunk_tile=0, chunk_wide=0, chunk_direct=0):
         torch = _torch()
         if not torch.cuda.is_available():
             raise RuntimeError("paper_1812_00367_amd needs a ROCm GPU; none is visible")
@@ -62,6 +67,7 @@ class Batch:
             eps=float(eps), eta=float(eta), eta_init=float(eta_init),
             dt_max_log2=self.dt_max_log2, dt_min_log2=self.dt_min_log2, jchunk=int(jchunk),
             items_per_job=int(items_per_job), partial_slots=int(partial_slots),
+            chunk_tile=int(chunk_tile), chunk_wide=int(chunk_wide), chunk_direct=int(chunk_direct),
             stream=ctypes.c_void_p(self.stream.cuda_stream))
         nbytes = ctypes.c_size_t(0)
         rc = self._lib.nb_batch_workspace_bytes(ctypes.byref(self._params), ctypes.byref(nbytes))

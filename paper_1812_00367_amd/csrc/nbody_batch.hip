@@ -210,32 +210,40 @@ __host__ __device__ inline int item_lanes(int64_t rem)
     return 64 / p;
 }
 
+// The batch constants of the work split.
+struct SplitCfg {
+    int lane_recs;   // j-records per lane of a work item
+    int target;      // work items per job at most (from j-chunks)
+    int mul_tile, mul_wide, mul_direct;  // chunk-length factors of the three classes
+    int64_t wide_min;                     // active bodies from which a job is wide
+};
+
 // Split of one job's evaluation: tiles = ceil(n_act / 64) i-tiles (of 128 for a wide
 // job, n_act >= wide_min), S j-chunks of jch bodies. S gives every lane about
 // `lane_recs` records (lane_recs 16 / W when W > 16 lanes share a body, so that a job
-// with one to three active bodies still spreads over several waves), times kWideRecs
-// in a wide item and kTileRecs in a tile item with fewer than 8 lanes per body:
-// longer chunks there amortise each item's set-up and leave fewer partial sums for
-// the finishing pass to add (measured: 4 for wide items, 2 for tile items), but no
-// more chunks than make `target` work items for the job. Depends on (n, n_act) and
-// the batch constants only.
-constexpr int kWideRecs = 4;
-constexpr int kTileRecs = 2;
+// with one to three active bodies still spreads over several waves), times the
+// factor of the job's class: a wide job, a job whose active bodies take fewer than 8
+// lanes each (tile items), or one whose take 8 or more (direct items). Longer chunks
+// amortise each item's set-up and leave fewer partial sums for the finishing pass;
+// shorter ones make more items. No more chunks than make `target` work items for
+// the job. Depends on (n, n_act) and the batch constants only.
 
 struct JobSplit {
     int64_t tiles, S, jch;
     bool wide;
 };
 
-__host__ __device__ inline JobSplit job_split(int64_t n, int64_t na, int lane_recs, int target,
-                                              int64_t wide_min)
+__host__ __device__ inline JobSplit job_split(int64_t n, int64_t na, const SplitCfg &cfg)
 {
+    const int lane_recs = cfg.lane_recs, target = cfg.target;
+    const int64_t wide_min = cfg.wide_min;
     JobSplit r;
     r.wide = na >= wide_min;
     const int64_t tw = r.wide ? 2 * kItemTile : kItemTile;
     r.tiles = (na + tw - 1) / tw;
     const int64_t W = r.wide ? 1 : item_lanes(na < 64 ? na : 64);
-    const int64_t per = (int64_t)lane_recs * (r.wide ? kWideRecs : W < 8 ? kTileRecs * W : (W < 16 ? W : 16));
+    const int64_t per = (int64_t)lane_recs * (r.wide ? cfg.mul_wide : W < 8 ? cfg.mul_tile * W
+                                                                     : cfg.mul_direct * (W < 16 ? W : 16));
     int64_t S = (n + per - 1) / per;
     const int64_t cap = (target + r.tiles - 1) / r.tiles;
     S = S < cap ? S : cap;
@@ -317,7 +325,7 @@ __device__ __forceinline__ void block_scan(int64_t (&v)[NV], int64_t (&tot)[NV],
 constexpr int kPlanBS = 256;
 
 __device__ __forceinline__ void plan_jobs(const Pool &P, const int32_t *__restrict__ jobs, int njobs,
-                                          int lane_recs, int target, int64_t wide_min, int count)
+                                          const SplitCfg cfg, int count)
 {
     constexpr int NW = kPlanBS / 64;
     __shared__ int64_t scr[NW][7], pre[NW + 1][7];
@@ -332,7 +340,7 @@ __device__ __forceinline__ void plan_jobs(const Pool &P, const int32_t *__restri
             na = P.j_nact[job];
             n = P.j_n[job];
             if (na > 0)
-                sp = job_split(n, na, lane_recs, target, wide_min);
+                sp = job_split(n, na, cfg);
         }
         const bool on = na > 0;
         // items per class: a wide job's tiles; else full tiles (and a tail of 9..63)
@@ -386,9 +394,9 @@ __device__ __forceinline__ void plan_jobs(const Pool &P, const int32_t *__restri
 }
 
 __global__ __launch_bounds__(kPlanBS) void k_plan(Pool P, const int32_t *__restrict__ jobs, int njobs,
-                                                  int lane_recs, int target, int64_t wide_min, int count)
+                                                  SplitCfg cfg, int count)
 {
-    plan_jobs(P, jobs, njobs, lane_recs, target, wide_min, count);
+    plan_jobs(P, jobs, njobs, cfg, count);
 }
 
 // Largest k in [0, count) with prefix[k] <= e (prefix ascending, prefix[0] = 0).
@@ -428,10 +436,10 @@ __device__ __forceinline__ const int64_t *cache_prefix(const int64_t *__restrict
 // job list changes, so a step touches only the jobs' bodies, not the whole pool).
 __global__ __launch_bounds__(kPlanBS) void k_bpredict_plan(Pool P, int64_t cap, double tick_size, int split,
                                                            const int32_t *__restrict__ jobs, int njobs,
-                                                           int lane_recs, int target, int64_t wide_min)
+                                                           SplitCfg cfg)
 {
     if (blockIdx.x == 0) {
-        plan_jobs(P, jobs, njobs, lane_recs, target, wide_min, 1);
+        plan_jobs(P, jobs, njobs, cfg, 1);
         return;
     }
     const int2 blk = P.pblk[blockIdx.x - 1];
@@ -1111,7 +1119,7 @@ struct nb_batch {
     hipStream_t st;
     Pool P;
     int64_t cap, partial_slots;
-    int lane_recs, target;
+    nb::SplitCfg split_cfg;
     int eval_grid, finish_grid;
     char msg[512];
     // host job table
@@ -1147,6 +1155,25 @@ constexpr int kDefaultTarget = 2048;
 
 int b_lane_recs(const nb_batch_params *p) { return p->jchunk > 0 ? p->jchunk : kDefaultLaneRecs; }
 int b_target(const nb_batch_params *p) { return p->items_per_job > 0 ? p->items_per_job : kDefaultTarget; }
+
+// Default chunk-length factors of the tile, wide and direct classes (measured on the
+// 512-cluster ensemble and the serving mix, against 1: wide 4 gave +4 %, then tile 2
+// +3 %; direct 2 or 1/2 were slower).
+constexpr int kDefaultMul[3] = {2, 4, 1};
+
+nb::SplitCfg b_split_cfg(const nb_batch_params *p)
+{
+    nb::SplitCfg c;
+    c.lane_recs = b_lane_recs(p);
+    c.target = b_target(p);
+    const int32_t m[3] = {p->chunk_tile, p->chunk_wide, p->chunk_direct};
+    c.mul_tile = m[0] > 0 ? m[0] : kDefaultMul[0];
+    c.mul_wide = m[1] > 0 ? m[1] : kDefaultMul[1];
+    c.mul_direct = m[2] > 0 ? m[2] : kDefaultMul[2];
+    // the wide class (two bodies per lane) is FP64 only
+    c.wide_min = p->precision == NB_SPLIT ? INT64_MAX : nb::kWideMin;
+    return c;
+}
 
 // Partial-sum slots that every step fits by construction: a job with t i-tiles of w
 // (64 or 128) bodies uses S n_act slots with S <= max(1, ceil(target / t)), i.e. at
@@ -1256,12 +1283,12 @@ const char *b_check_params(const nb_batch_params *p)
         return "jchunk must be a multiple of 64 in [0, 2^20] (0 = default)";
     if (p->items_per_job < 0 || p->items_per_job > (1 << 14))
         return "items_per_job must be in [0, 16384] (0 = default)";
+    if (p->chunk_tile < 0 || p->chunk_tile > 64 || p->chunk_wide < 0 || p->chunk_wide > 64 ||
+        p->chunk_direct < 0 || p->chunk_direct > 64)
+        return "chunk_tile, chunk_wide and chunk_direct must be in [0, 64] (0 = default)";
     if (p->partial_slots < 0) return "partial_slots must be >= 0";
     return nullptr;
 }
-
-// The wide class (two bodies per lane) is FP64 only.
-int64_t b_wide_min(const nb_batch *b) { return b->p.precision == NB_SPLIT ? INT64_MAX : nb::kWideMin; }
 
 // Launches of one evaluation over the jobs in `list` (n_list entries, device array)
 // whose n_act is in j_nact, then the finishing pass in `mode`. No host work between.
@@ -1271,8 +1298,8 @@ nb_status b_eval_finish(nb_batch *b, const int32_t *list, int n_list, int mode, 
     const bool split = b->p.precision == NB_SPLIT;
     const int L = b->p.dt_max_log2 - b->p.dt_min_log2;
     if (!planned)
-        hipLaunchKernelGGL(nb::k_plan, dim3(1), dim3(nb::kPlanBS), 0, b->st, b->P, list, n_list, b->lane_recs,
-                           b->target, b_wide_min(b), count);
+        hipLaunchKernelGGL(nb::k_plan, dim3(1), dim3(nb::kPlanBS), 0, b->st, b->P, list, n_list, b->split_cfg,
+                           count);
     if (split) {
         const float e2 = (float)(b->p.eps * b->p.eps);
         hipLaunchKernelGGL(nb::k_beval_split, dim3(b->eval_grid), dim3(64), 0, b->st, b->P, e2);
@@ -1319,7 +1346,7 @@ nb_status b_launch_step(nb_batch *b)
                        b->p.dt_max_log2 - b->p.dt_min_log2);
     hipLaunchKernelGGL(nb::k_bpredict_plan, dim3(1 + b->npblk), dim3(nb::kPlanBS), 0, b->st,
                        b->P, b->cap, ldexp(1.0, b->p.dt_min_log2), (int)split, (const int32_t *)b->d_jobs,
-                       b->njobs, b->lane_recs, b->target, b_wide_min(b));
+                       b->njobs, b->split_cfg);
     B_HIP(b, hipGetLastError());
     return b_eval_finish(b, b->d_jobs, b->njobs, nb::kStep, 1, true);
 }
@@ -1437,8 +1464,7 @@ nb_status nb_batch_create(const nb_batch_params *p, void *d_workspace, size_t by
     b->st = (hipStream_t)p->stream;
     b->cap = p->capacity;
     b->partial_slots = b_partial_slots(p);
-    b->lane_recs = b_lane_recs(p);
-    b->target = b_target(p);
+    b->split_cfg = b_split_cfg(p);
     b_layout(p, &b->P, &b->d_jobs, &b->d_one, (char *)d_workspace);
     const size_t J = (size_t)p->max_jobs;
     b->off.assign(J, 0);

@@ -92,41 +92,53 @@ def tune(sim, sizes=None, seed=20, shapes=SHAPES, targets=TARGETS, log=None):
 
 BATCH_JCHUNKS = [64, 128, 192, 256]
 BATCH_TARGETS = [512, 2048, 8192]
+# chunk-length factors of the tile, wide and direct item classes
+BATCH_FACTORS = [(1, 4, 1), (2, 4, 1), (4, 4, 1), (2, 2, 1), (2, 8, 1), (2, 4, 2)]
 
 
-def tune_batch(clusters, tick_end, precision, jchunks=BATCH_JCHUNKS, targets=BATCH_TARGETS,
-               steps_per_call=32, log=None):
-    """Time the batch path on an ensemble for every (jchunk, items_per_job) pair and
-    return (best (jchunk, items_per_job), {pair: interactions/s}). `clusters` is a
-    list of objects with m, x, v (one job each), all integrated to tick_end."""
+def batch_configs(sweep):
+    """Batch keyword arguments to time: sweep "split" covers (jchunk, items_per_job),
+    "factors" the class factors (chunk_tile, chunk_wide, chunk_direct) at the default
+    jchunk and items_per_job."""
+    if sweep == "split":
+        return [dict(jchunk=jc, items_per_job=tg) for jc in BATCH_JCHUNKS for tg in BATCH_TARGETS]
+    if sweep == "factors":
+        return [dict(chunk_tile=t, chunk_wide=w, chunk_direct=d) for t, w, d in BATCH_FACTORS]
+    raise ValueError(f"unknown sweep {sweep!r}")
+
+
+def tune_batch(clusters, tick_end, precision, configs, steps_per_call=32, log=None):
+    """Time the batch path on an ensemble once for every configuration (a dict of
+    Batch keyword arguments) and return (best configuration, [interactions/s per
+    configuration]). `clusters` is a list of objects with m, x, v (one job each), all
+    integrated to tick_end."""
     import time
 
     import torch
 
     from .batch import Batch
     cap = sum(len(ic.m) for ic in clusters)
-    rates = {}
-    for jc in jchunks:
-        for tg in targets:
-            b = Batch(cap, len(clusters), precision=precision, jchunk=jc, items_per_job=tg)
-            for ic in clusters:
-                if b.add(ic.m, ic.x, ic.v, tick_end) is None:
-                    raise RuntimeError("ensemble does not fit")
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            inter = 0
-            while True:
-                _, _, _, it, taken = b.run_steps(steps_per_call)
-                inter += it
-                if taken < steps_per_call:
-                    break
-            dt = time.perf_counter() - t0
-            rates[(jc, tg)] = inter / dt
-            if log:
-                log(f"jchunk={jc} items_per_job={tg}: {inter / dt:.3e} interactions/s ({dt:.2f} s)")
-            b.close()
-    best = max(rates, key=rates.get)
-    return best, rates
+    rates = []
+    for cfg in configs:
+        b = Batch(cap, len(clusters), precision=precision, **cfg)
+        for ic in clusters:
+            if b.add(ic.m, ic.x, ic.v, tick_end) is None:
+                raise RuntimeError("ensemble does not fit")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        inter = 0
+        while True:
+            _, _, _, it, taken = b.run_steps(steps_per_call)
+            inter += it
+            if taken < steps_per_call:
+                break
+        dt = time.perf_counter() - t0
+        rates.append(inter / dt)
+        if log:
+            log(f"{cfg}: {inter / dt:.3e} interactions/s ({dt:.2f} s)")
+        b.close()
+    best = max(range(len(configs)), key=lambda k: rates[k])
+    return configs[best], rates
 
 
 def main():
@@ -137,6 +149,8 @@ def main():
     ap.add_argument("--batch", type=int, default=0,
                     help="tune the batch path instead, on an ensemble of this many Plummer "
                          "clusters (N log-uniform in [256, 16384], Kroupa masses) to t = 0.125")
+    ap.add_argument("--sweep", choices=("split", "factors"), default="split",
+                    help="batch: sweep (jchunk, items_per_job) or the item-class chunk factors")
     args = ap.parse_args()
     if args.batch:
         import nbody_inputs as ni
@@ -148,10 +162,11 @@ def main():
             s = int(g.integers(0, 2**31 - 1))
             clusters.append(ni.plummer(n, s, masses=ni.kroupa_masses(n, s + 1)))
         prec = nb.NB_SPLIT if args.precision == "split" else nb.NB_FP64
-        best, rates = tune_batch(clusters, 1 << 37, prec, log=lambda m: print(m, flush=True))
-        print(json.dumps({"clusters": args.batch, "precision": args.precision,
-                          "best": {"jchunk": best[0], "items_per_job": best[1]},
-                          "rates": {f"{k[0]}/{k[1]}": v for k, v in rates.items()}}), flush=True)
+        configs = batch_configs(args.sweep)
+        best, rates = tune_batch(clusters, 1 << 37, prec, configs, log=lambda m: print(m, flush=True))
+        print(json.dumps({"clusters": args.batch, "precision": args.precision, "sweep": args.sweep,
+                          "best": best, "rates": [dict(c, rate=r) for c, r in zip(configs, rates)]}),
+              flush=True)
         return
     import nbody_inputs as ni
     import paper_1812_00367_amd as nb

@@ -108,10 +108,15 @@ def test_batch_workspace_bytes_and_argument_checks(lib):
     assert out.value == fp64  # raised to the bound
     assert lib.nb_batch_workspace_bytes(ctypes.byref(_bparams(items_per_job=64)), ctypes.byref(out)) == 0
     assert out.value < fp64
+    # the chunk factors change the split, not the workspace
+    assert lib.nb_batch_workspace_bytes(ctypes.byref(_bparams(chunk_tile=1, chunk_wide=8, chunk_direct=64)),
+                                        ctypes.byref(out)) == 0
+    assert out.value == fp64
     bad = [dict(capacity=0), dict(capacity=(1 << 30) + 1), dict(max_jobs=0),
            dict(max_jobs=(1 << 16) + 1), dict(eps=-1.0), dict(eta=float("inf")),
            dict(dt_min_log2=-70), dict(precision=3), dict(jchunk=100), dict(jchunk=-64),
-           dict(items_per_job=-1), dict(items_per_job=(1 << 14) + 1), dict(partial_slots=-5)]
+           dict(items_per_job=-1), dict(items_per_job=(1 << 14) + 1), dict(partial_slots=-5),
+           dict(chunk_tile=-1), dict(chunk_wide=65), dict(chunk_direct=-2)]
     for kw in bad:
         assert lib.nb_batch_workspace_bytes(ctypes.byref(_bparams(**kw)), ctypes.byref(out)) == 1, kw
     b = ctypes.c_void_p(0)

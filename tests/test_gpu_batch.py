@@ -66,12 +66,16 @@ def states(b, jobs):
 
 
 # --------------------------------------------------------------- oracle parity --
-def test_batch_jobs_match_oracle(nb):
+# default chunk factors of the item classes, and another setting of all three
+@pytest.mark.parametrize("factors", [None, (1, 8, 2)])
+def test_batch_jobs_match_oracle(nb, factors):
     sizes = [70, 200, 333, 1024, 64, 1]
     # end times are whole multiples of dt_max, where every body of a job is synchronised
     ends = [1 << L, 2 << L, 3 << L, 1 << L, 2 << L, 1 << L]
     ics = [cluster(n, 100 + k) for k, n in enumerate(sizes)]
-    b = make_batch(nb, sum(sizes) + 500, 8)
+    kw = {} if factors is None else dict(chunk_tile=factors[0], chunk_wide=factors[1],
+                                         chunk_direct=factors[2])
+    b = make_batch(nb, sum(sizes) + 500, 8, **kw)
     jobs = []
     for ic, te in zip(ics, ends):
         jobs.append(b.add(ic.m, ic.x, ic.v, te))
