@@ -355,3 +355,55 @@ def test_batch_active_sets_of_large_jobs(nb):
             checked[j] += 1
     say("large-job active sets checked per job:", checked)
     assert all(v > 0 for v in checked.values())
+
+
+# ------------------------------------- the full ensemble of the batched benchmark --
+def test_c4_full_ensemble_sampled(nb):
+    """The 512-cluster ensemble of `bench.py --config c4` (2.04 M bodies, the same
+    batch parameters): the start-up a, j, s, phi of sampled bodies of nine sampled
+    clusters (smallest, median, largest, and others) against the oracle on the same
+    inputs, then ten batch steps replayed: one oracle block step from each sampled
+    cluster's state before the step gives the same block time and active set (bit
+    exact), the same new levels, and positions and velocities within 1e-12."""
+    import bench
+    from test_gpu_parity import TOL_EVAL, eval_errors
+    ics = bench.ensemble_clusters(512)
+    ns = np.array([ic.m.size for ic in ics])
+    tick_end = int(round(0.25 * 2.0 ** -DT_MIN))
+    b = nb.Batch(int(ns.sum()), 512, eps=bench.EPS, dt_max_log2=bench.DT_MAX, dt_min_log2=bench.DT_MIN)
+    jobs = [b.add(ic.m, ic.x, ic.v, tick_end) for ic in ics]
+    assert all(j is not None for j in jobs)
+    order = np.argsort(ns, kind="stable")
+    sample = [int(order[0]), int(order[1]), int(order[255]), int(order[256]), int(order[-2]),
+              int(order[-1]), 17, 100, 333]
+    say("c4 sampled clusters", [(k, int(ns[k])) for k in sample])
+    for k in sample:
+        st = {key: host(t) for key, t in b.get(jobs[k]).items()}
+        n = int(ns[k])
+        pick = np.unique(np.linspace(0, n - 1, min(n, 64)).astype(np.int32))
+        ref = oracle.evaluate(ics[k].m, ics[k].x, ics[k].v, st["a"], bench.EPS, idx=pick)
+        got = np.concatenate([st["a"], st["j"], st["s"], st["phi"][None, :]])[:, pick]
+        errs = eval_errors(got, ref)
+        assert max(errs) <= TOL_EVAL, (k, n, errs)
+    for step in range(10):
+        before = {k: {key: host(t) for key, t in b.get(jobs[k]).items()} for k in sample}
+        nact, tnext, err, _ = b.step()
+        for k in sample:
+            j = jobs[k]
+            assert err[j] == 0, (step, k, err[j])
+            s0 = before[k]
+            ost = oracle.State(m=s0["m"], x=s0["x"], v=s0["v"], a=s0["a"], j=s0["j"], s=s0["s"],
+                               c=s0["c"], a4n=s0["a4n"], a5n=s0["a5n"], tick=s0["tick"],
+                               level=s0["level"])
+            idx, tn = oracle.active(ost.tick, ost.level, L)
+            assert nact[j] == len(idx) and tnext[j] == tn, (step, k)
+            xp, vp, ap = oracle.predict(ost.tick, tn, DT_MIN, ost.x, ost.v, ost.a, ost.j, ost.s, ost.c)
+            anew = oracle.evaluate(ost.m, xp, vp, ap, bench.EPS, idx=idx)
+            oracle.correct(ost, idx, tn, DT_MIN, anew)
+            oracle.timesteps(ost, idx, 0, 0.45, 0.01, DT_MAX, DT_MIN)
+            s1 = {key: host(t) for key, t in b.get(j).items()}
+            assert np.array_equal(s1["tick"], ost.tick), (step, k)
+            assert np.array_equal(s1["level"], ost.level), (step, k)
+            assert np.abs(s1["x"] - ost.x).max() < 1e-12, (step, k)
+            assert np.abs(s1["v"] - ost.v).max() < 1e-12, (step, k)
+    b.close()
