@@ -301,6 +301,41 @@ def test_c1_block_steps_match_oracle(nb):
     assert abs((e1 - e0) - (sum(r1) - sum(ro))) < 1e-9 * abs(sum(ro))
 
 
+def test_c1_per_step_replay_errors(nb):
+    """W1 block steps on the GPU, replayed: at every block step the oracle evaluates
+    the active bodies from the GPU's own predicted positions, velocities and
+    accelerations (identical inputs), and every per-body relative error of a, j, s
+    (and phi) stays within the FP64 bound. Prints the max and p99 over all steps
+    and bodies."""
+    ic, sim = _c1(nb)
+    t_end = 1 << L
+    sim.start()
+    errs = {"a": [], "j": [], "s": [], "phi": []}
+    steps = inter = 0
+    while True:
+        idx, tn = sim.active()
+        if len(idx) == 0 or tn > t_end:
+            break
+        sim.predict(tn)
+        got = host(sim.evaluate(idx))
+        xp, vp, ap = (host(t) for t in sim.get_predicted())
+        ref = oracle.evaluate(ic.m, xp, vp, ap, 1e-4, idx=host(idx))
+        errs["a"].append(rel_vec_err(got[0:3], ref[0:3]))
+        errs["j"].append(rel_vec_err(got[3:6], ref[3:6]))
+        errs["s"].append(rel_vec_err(got[6:9], ref[6:9]))
+        errs["phi"].append(np.abs(got[9] - ref[9]) / np.abs(ref[9]))
+        sim.correct(idx, tn)
+        sim.timesteps(idx)
+        steps += 1
+        inter += len(idx) * ic.m.size
+    summary = {k: (float(np.concatenate(v).max()), float(np.percentile(np.concatenate(v), 99)))
+               for k, v in errs.items()}
+    say("c1 replay: steps", steps, "interactions", inter, "max / p99 relative error", summary)
+    assert steps == 215
+    for k, (mx, _) in summary.items():
+        assert mx <= TOL_EVAL, (k, mx)
+
+
 def test_determinism_and_checkpoint_resume(nb):
     ic, sim = _c1(nb, n=512, seed=11)
     sim.start()
