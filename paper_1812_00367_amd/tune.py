@@ -10,11 +10,13 @@ covers active sets up to the geometric midpoint to the next tuned size.
 
 prints the table as JSON (and as a C initializer).
 
-    python -m paper_1812_00367_amd.tune --batch 128 [--precision fp64|split]
+    python -m paper_1812_00367_amd.tune --batch 128 [--sweep split|factors] [--precision fp64|split]
 
 tunes the batch path instead: it times an ensemble of clusters for each pair of
-(j-records per lane, work items per job) and prints the fastest pair, to be passed
-to Batch(jchunk=..., items_per_job=...) / nb_batch_params.
+(j-records per lane, work items per job), or for each setting of the chunk-length
+factors of the three item classes, and prints the fastest, to be passed to
+Batch(jchunk=..., items_per_job=..., chunk_tile=..., chunk_wide=..., chunk_direct=...)
+/ nb_batch_params.
 """
 from __future__ import annotations
 
