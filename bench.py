@@ -100,7 +100,7 @@ def parse():
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+        print("bench.py runs on exactly one GPU: there is no multi-GPU path "
               "(the design notes describe how the evaluation would shard).", file=sys.stderr)
         sys.exit(2)
     import numpy as np
