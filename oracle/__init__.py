@@ -11,8 +11,10 @@ Parity status of each function (what pins it is in the tests under ``tests/``):
   evaluate_crackle  pinned  (third time derivative by finite differences, Newton's law)
   predict    pinned  (exact on polynomial motion of degree <= 5)
   correct    pinned  (exact on polynomial accelerations; interpolation exact)
-  timesteps  block rules pinned by hand cases; the criterion's formula itself is a
-             reading of the literature: parity unpinned
+  timesteps  pinned  (block rules by hand cases; the step criterion and the start
+             rule by the circular-orbit closed form: dt = eta / omega,
+             eta_init / omega). Which criterion the method uses is a reading of
+             the literature, since the paper prints none.
   active     pinned  (brute force by definition on small random cases)
   energy     pinned  (closed form two-body, Plummer virial values)
   integrate  pinned  (closed-form Kepler orbit, 6th-order convergence)

@@ -313,9 +313,10 @@ static double norm3(const double *p, int64_t n, int64_t i)
  * init the level must also divide the body's time.
  * A body that fits no level up to L (dt_min) is a numeric failure; its level is
  * clamped to L. Zero or non-finite denominators mean "no constraint" (level 0).
- * Readings: exponent form and eta_init start as stated above. Parity unpinned:
- * the paper gives neither formula; tests pin only the block rules, the power-of-two
- * quantisation and the time divisibility by hand cases.
+ * Readings: exponent form and eta_init start as stated above; the paper gives
+ * neither formula. Pins: on a circular orbit (|a^(k)| = |a| omega^k) the criterion
+ * is eta / omega and the start rule eta_init / omega, whatever the radius; the block
+ * rules, the power-of-two quantisation and the time divisibility by hand cases.
  */
 int nbo_timesteps(int64_t n, int64_t n_act, const int32_t *idx, int init,
                   const int64_t *tick, int32_t *level, const double *a,

@@ -11,9 +11,10 @@ integration loop.
   * active set: brute force over the definition on random block states;
   * energy: closed-form two-body value;
   * integration: closed-form Kepler orbit (Kepler's equation), 6th-order
-    convergence with fixed steps, energy conservation, block invariants.
-The step criterion's formula is a reading of the literature, not a result the
-paper fixes: its parity is unpinned beyond the structural checks here.
+    convergence with fixed steps, energy conservation, block invariants;
+  * step criterion and start rule: the circular-orbit closed form (eta / omega and
+    eta_init / omega at any radius); the criterion itself is a reading of the
+    literature, since the paper prints no formula.
 """
 import math
 
@@ -187,6 +188,46 @@ def test_initial_step_rule():
                    tick=_ticks(8), level=0)
     oracle.timesteps(st, [0], 1, ETA, 0.01, -3, DT_MIN_LOG2)
     assert st.level[0] == 8
+
+
+def _circular_derivatives(omega, radius, phase, rot):
+    """a, a', ..., a^(5) of uniform circular motion at angular speed omega, radius
+    radius and phase phase, in the plane turned by the rotation matrix rot: with
+    r = radius (cos th, sin th, 0), a = -omega^2 r and the k-th derivative turns the
+    vector by k quarter turns and scales it by omega^k."""
+    out = []
+    for k in range(6):
+        th = phase + k * math.pi / 2
+        out.append(rot @ (-(omega ** (k + 2)) * radius * np.array([math.cos(th), math.sin(th), 0.0])))
+    return out
+
+
+def _rotation(g):
+    q, _ = np.linalg.qr(g.standard_normal((3, 3)))
+    return q
+
+
+@pytest.mark.parametrize("init", [0, 1])
+def test_step_criterion_circular_orbit_closed_form(init):
+    """On a circular orbit every derivative of the acceleration has magnitude
+    |a| omega^k, so the sixth-order Aarseth criterion gives eta / omega exactly and the
+    start rule gives eta_init / omega (the orbital time scale, whatever the radius).
+    The step is the largest power of two not above that. Time scales are placed
+    0.15 and 0.85 of an octave above a power of two, so a factor of 2^(1/3) either
+    way (a dropped term, a swapped derivative) or a wrong power of omega moves the
+    level."""
+    g = ni.rng(41)
+    eta_init = 0.01
+    for e in (4.15, 4.85, 7.5, 12.15, 12.85, 21.15, 21.85, 33.15, 36.85):
+        for radius in (1e-3, 1.0, 250.0):
+            # time scale 2^-e of the tested rule
+            omega = (eta_init if init else ETA) * 2.0 ** e
+            a, j, s, c, a4, a5 = _circular_derivatives(omega, radius, float(g.uniform(0, 6.3)),
+                                                       _rotation(g))
+            st = _ts_state(a, j, s, c, np.linalg.norm(a4), np.linalg.norm(a5), tick=0, level=0)
+            oracle.timesteps(st, [0], init, ETA, eta_init, -3, DT_MIN_LOG2)
+            # largest 2^(-3-k) <= 2^-e
+            assert st.level[0] == math.ceil(e) - 3, (e, radius, init)
 
 
 def test_active_set_brute_force():

@@ -44,6 +44,14 @@ MUTANTS = [
      "(t % ((int64_t)1 << (L - kold + 1))) == 0", "(t % ((int64_t)1 << (L - kold))) == 0"),
     ("block rule: cube missing", "ldexp(1.0, 3 * (dt_max_log2 - k)) <= qv",
      "ldexp(1.0, 2 * (dt_max_log2 - k)) <= qv"),
+    ("step criterion: dropped sqrt(|a||s|) term", "const double num = sqrt(an * sn) + jn;",
+     "const double num = jn;"),
+    ("step criterion: 4th and 5th derivatives swapped",
+     "const double den = sqrt(cn * a5n[i]) + a4n[i];",
+     "const double den = sqrt(cn * a4n[i]) + a5n[i];"),
+    ("start rule: snap time scale without its square root", "sqrt(an / sn)", "(an / sn)"),
+    ("start rule: max instead of min", "d0 = eta_init * (ra < rs ? ra : rs);",
+     "d0 = eta_init * (ra > rs ? ra : rs);"),
     ("active set: max instead of min", "if (e < tn)", "if (e > tn || tn == INT64_MAX)"),
     ("energy: potential double counted", "cs_add(&ep, -0.5 * m[i] * phi[i]);",
      "cs_add(&ep, -1.0 * m[i] * phi[i]);"),
@@ -67,6 +75,9 @@ PINS = [
     lambda: tg.test_corrector_polynomial_exactness(4, -7),
     lambda: tg.test_block_rule_shrink_is_free(),
     lambda: tg.test_block_rule_grow_one_level_only_at_even_time(),
+    lambda: tg.test_initial_step_rule(),
+    lambda: tg.test_step_criterion_circular_orbit_closed_form(0),
+    lambda: tg.test_step_criterion_circular_orbit_closed_form(1),
     lambda: tg.test_active_set_brute_force(),
     lambda: tg.test_energy_two_body_closed_form(),
     lambda: ti.test_plummer_henon_units(),
