@@ -228,11 +228,12 @@ nb_status nb_energy(nb_ctx *ctx, int64_t tick, double *h_ekin, double *h_epot);
  * Many independent systems ("jobs") of uneven size resident in one workspace and
  * advanced together (block steps as in the paper's section "Code implementation").
  * A batch step gives each job its own next block step (its own block time and
- * active set, as nb_step does for one system) with five kernel launches for all
- * jobs and no host work in between: active sets, prediction, a work split, one
- * persistent evaluation over work items (job, i-tile of up to 128 active bodies,
- * j-chunk) of three item classes (two in split precision), and a per-body pass
- * that sums the partials in a fixed order, corrects and sets the new levels. A
+ * active set, as nb_step does for one system) with four kernel launches for all
+ * jobs and no host work in between: active sets; prediction, with the work split
+ * built beside it; one persistent evaluation over work items (job, i-tile of up to
+ * 128 active bodies, j-chunk) of three item classes (two in split precision); and a
+ * per-body pass that sums the partials in a fixed order, corrects and sets the new
+ * levels. A
  * job's split depends only on its own (n, n_act) and the batch constants, so its
  * results are bitwise the same alone and in any mix of jobs.
  * Jobs are admitted into a fixed pool of bodies (first fit): nb_batch_add fails with
