@@ -553,28 +553,47 @@ def serving_workload(rates, count=24, budget_gib=32.0, slots=64, t_end=1.0, prec
     return res
 
 
+def cpu_model():
+    """The host CPU's model name (from /proc/cpuinfo), or the platform's string."""
+    import platform
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
+
+
 def cpu_baseline(ic, n, seconds):
-    """The oracle's evaluation on a bounded sample of the active set."""
+    """The oracle's evaluation on a bounded sample of the active set, on every host
+    core (the reported value), then on one core over a sample a fifth as long."""
     import numpy as np
 
     import nbody_inputs as ni
     import oracle
     threads = oracle.default_threads()
     ap = ni.plummer_mean_field_acc(ic.x)
-    probe = 64
-    t0 = time.perf_counter()
-    oracle.evaluate(ic.m, ic.x, ic.v, ap, EPS, idx=np.arange(probe, dtype=np.int32),
-                    nthreads=threads)
-    dt = time.perf_counter() - t0
-    k = int(min(n, max(probe, probe * seconds / max(dt, 1e-6))))
-    k = max(threads, k // threads * threads)
-    idx = ni.active_subset(n, k, 99)
-    t0 = time.perf_counter()
-    oracle.evaluate(ic.m, ic.x, ic.v, ap, EPS, idx=idx, nthreads=threads)
-    dt = time.perf_counter() - t0
+
+    def timed(k, nthreads):
+        idx = ni.active_subset(n, k, 99)
+        t0 = time.perf_counter()
+        oracle.evaluate(ic.m, ic.x, ic.v, ap, EPS, idx=idx, nthreads=nthreads)
+        return time.perf_counter() - t0
+
+    probe = min(n, 64)
+    k = int(min(n, max(probe, probe * seconds / max(timed(probe, threads), 1e-6))))
+    k = min(n, max(threads, k // threads * threads))
+    dt = timed(k, threads)
+    per_body_one_core = dt * threads / k   # seconds, if the threads scaled perfectly
+    k1 = int(min(n, max(1, 0.2 * seconds / per_body_one_core)))
+    dt1 = timed(k1, 1)
     return {"value": k * n / dt, "unit": "interactions/s", "cores": threads, "kind": "oracle",
-            "sample": f"{k} active bodies x {n} bodies (plummer-65536), "
-                      f"{k * n:.3e} interactions in {dt:.1f} s"}
+            "sample": f"{k} active bodies x {n} bodies (plummer-{n}), "
+                      f"{k * n:.3e} interactions in {dt:.1f} s",
+            "cpu": cpu_model(), "one_core_value": k1 * n / dt1,
+            "one_core_sample": f"{k1} active bodies x {n} bodies in {dt1:.1f} s"}
 
 
 if __name__ == "__main__":
