@@ -56,6 +56,38 @@ def rel_vec_err(got, ref):
     return np.linalg.norm(got - ref, axis=0) / np.linalg.norm(ref, axis=0)
 
 
+def error_stats(got, ref):
+    """(p50, p99, max) of the per-body relative errors of a, j and s."""
+    out = []
+    for c in range(3):
+        e = rel_vec_err(got[3 * c:3 * c + 3], ref[3 * c:3 * c + 3])
+        out.append((float(np.median(e)), float(np.percentile(e, 99)), float(e.max())))
+    return out
+
+
+def condition_numbers(m, xp, vp, ap, eps, idx):
+    """kappa_i = sum_j |q_ij| / |q_i| for q = a, j, s of the bodies idx (a report of
+    how much the sums cancel, not a reference: the oracle is the reference)."""
+    kap = np.zeros((3, len(idx)))
+    for col, i in enumerate(idx):
+        r = xp - xp[:, i:i + 1]
+        v = vp - vp[:, i:i + 1]
+        a = ap - ap[:, i:i + 1]
+        R = (r * r).sum(0) + eps * eps
+        mm = m.copy()
+        mm[i] = 0.0
+        R[i] = 1.0
+        m3 = mm * R ** -1.5
+        alpha = (r * v).sum(0) / R
+        beta = ((v * v).sum(0) + (r * a).sum(0)) / R + alpha * alpha
+        A = m3 * r
+        J = m3 * v - 3 * alpha * A
+        S = m3 * a - 6 * alpha * J - 3 * beta * A
+        for c, q in enumerate((A, J, S)):
+            kap[c, col] = np.linalg.norm(q, axis=0).sum() / np.linalg.norm(q.sum(1))
+    return kap
+
+
 def eval_errors(got, ref):
     return (rel_vec_err(got[0:3], ref[0:3]).max(), rel_vec_err(got[3:6], ref[3:6]).max(),
             rel_vec_err(got[6:9], ref[6:9]).max(),
@@ -401,4 +433,9 @@ def test_c2_full_size_sampled(nb, n_act):
     ref = oracle.evaluate(ic.m, ic.x, ic.v, ap, 1e-4, idx=idx[pick])
     errs = eval_errors(got[:, pick], ref)
     say("c2 errors", n_act, errs)
+    stats = error_stats(got[:, pick], ref)
+    kap = condition_numbers(ic.m, ic.x, ic.v, ap, 1e-4, idx[pick][:64])
+    for c, q in enumerate("ajs"):
+        say(f"c2 n_act {n_act} {q}: relative error p50 {stats[c][0]:.2e} p99 {stats[c][1]:.2e} "
+            f"max {stats[c][2]:.2e}; kappa p50 {np.median(kap[c]):.1f} max {kap[c].max():.1f}")
     assert max(errs) <= TOL_EVAL, errs
