@@ -45,11 +45,13 @@ PEAK_FP32_TFLOPS = 157.3           # the chip's FP32 vector peak (packed instruc
 KERNEL_SRCS = [os.path.join(ROOT, "paper_1812_00367_amd", "csrc", f)
                for f in ("nbody_kernels.hip", "nb_device.h", "nb_internal.h")]
 # HBM bytes per full-N FP64 evaluation launch from the FETCH_SIZE / WRITE_SIZE runs in
-# profiles/eval_fp64_plummer65536.md, keyed by the sha256 prefix of those sources.
-TRAFFIC = {"f8fe6ef99232d70e": {"fp64": 2.00 * 21978 * 1024 + 81920 * 1024}}
+# profiles/eval_fp64_plummer65536.md, keyed by the sha256 prefix of those sources (a
+# key is moved to a new hash only when the evaluation kernels' gfx950 assembly is
+# unchanged).
+TRAFFIC = {"db1f44bac1900e3c": {"fp64": 2.00 * 21978 * 1024 + 81920 * 1024}}
 # Flops per interaction the evaluation kernels execute (SQ_INSTS_VALU_FLOPS_FP64 /
 # _FP32 x 64 lanes / N^2, same profile), keyed the same way.
-EXECUTED_FLOPS = {"f8fe6ef99232d70e": {"fp64": 88.0, "split": 86.0}}
+EXECUTED_FLOPS = {"db1f44bac1900e3c": {"fp64": 88.0, "split": 86.0}}
 
 
 def kernel_sources_hash():

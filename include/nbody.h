@@ -204,7 +204,9 @@ nb_status nb_eval_table(nb_ctx *ctx, const int32_t *h_rows, int32_t nrows);
 
 /* Hermite 6th-order corrector of the bodies of the last nb_evaluate (same d_idx,
  * n_act) to tick, using that evaluation. Updates x, v, a, j, s, c, a4n, a5n and
- * sets their time to tick. Asynchronous. */
+ * sets their time to tick. Asynchronous. The kernel checks that d_idx is strictly
+ * ascending (a body listed twice would be corrected twice): otherwise the next
+ * waiting call returns NB_ERR_ARG and the listed bodies' state is undefined. */
 nb_status nb_correct(nb_ctx *ctx, const int32_t *d_idx, int64_t n_act, int64_t tick);
 
 /* New step levels of the bodies d_idx at their current time: the 6th-order

@@ -137,7 +137,8 @@ nb_status sync_status(nb_ctx *c)
     if (e[nb::kErrIndex] || e[nb::kErrLevel] || e[nb::kErrNumeric] || e[nb::kErrDtMin]) {
         nb_status s;
         if (e[nb::kErrIndex])
-            s = fail(c, NB_ERR_ARG, "an index list entry is outside [0, n)");
+            s = fail(c, NB_ERR_ARG, "an index list entry is outside [0, n), or the list given to nb_correct is "
+                                    "not strictly ascending");
         else if (e[nb::kErrLevel])
             s = fail(c, NB_ERR_ARG, "a body's time or level is inconsistent with the call "
                                     "(level outside [0, L], or a body ahead of the target time)");

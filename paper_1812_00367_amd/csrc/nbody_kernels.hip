@@ -257,7 +257,8 @@ __global__ __launch_bounds__(256) void k_correct(Arrays A, int n, const int32_t 
     if (q >= n_act)
         return;
     const int i = idx[q];
-    if ((unsigned)i >= (unsigned)n) {
+    // a body listed twice would be corrected twice: the list must be strictly ascending
+    if ((unsigned)i >= (unsigned)n || (q > 0 && idx[q - 1] >= i)) {
         raise_err(A.status, kErrIndex);
         return;
     }

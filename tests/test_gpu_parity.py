@@ -414,6 +414,16 @@ def test_errors_are_reported(nb):
     with pytest.raises(nb.NBodyError) as e:
         sim.correct(np.arange(4, dtype=np.int32), 1 << 10)
     assert e.value.status == 4
+    # a list that is not strictly ascending is refused by the corrector's check
+    for dup in (np.array([3, 5, 5, 9], np.int32), np.array([7, 2, 11], np.int32)):
+        sim2 = make_sim(nb, n)
+        sim2.set_state(ic.m, ic.x, ic.v, a=ap)
+        sim2.predict(1 << 10)
+        sim2.evaluate(dup)
+        sim2.correct(dup, 1 << 10)
+        with pytest.raises(nb.NBodyError) as e:
+            sim2.energy(1 << 10)
+        assert e.value.status == 1 and "ascending" in str(e.value), str(e.value)
 
 
 # --------------------------------------------------- full-size, sampled outputs --
