@@ -426,6 +426,35 @@ def test_errors_are_reported(nb):
         assert e.value.status == 1 and "ascending" in str(e.value), str(e.value)
 
 
+# ------------------------------------------------ a large system, sampled outputs --
+def test_large_system_sampled(nb):
+    """2^25 + 777 bodies (a 13 GB workspace, 2.7 GB of j-records, so byte offsets
+    pass 2^31): the active set of a random block state bit-exact against the
+    oracle, then the prediction of every body and the evaluation of 64 active
+    bodies, eight of them sampled against the oracle."""
+    n = (1 << 25) + 777
+    say("large system", n)
+    tick, level = ni.block_state(n, 505, L, max_level=16)
+    ic = ni.plummer(n, 5)
+    ap = ni.plummer_mean_field_acc(ic.x)
+    sim = make_sim(nb, n, eps=1e-4, partial_slots=1 << 20)
+    sim.set_state(ic.m, ic.x, ic.v, a=ap, tick=tick, level=level)
+    idx, tn = sim.active()
+    ridx, rtn = oracle.active(tick, level, L)
+    assert tn == rtn
+    assert np.array_equal(host(idx), ridx)
+    sim.set_state(ic.m, ic.x, ic.v, a=ap)
+    sim.predict(0)
+    act = ni.active_subset(n, 64, 506)
+    got = host(sim.evaluate(act))
+    pick = np.arange(0, 64, 8)
+    ref = oracle.evaluate(ic.m, ic.x, ic.v, ap, 1e-4, idx=act[pick])
+    errs = eval_errors(got[:, pick], ref)
+    say("large system errors", errs)
+    assert max(errs) <= TOL_EVAL, errs
+    del sim
+
+
 # --------------------------------------------------- full-size, sampled outputs --
 @pytest.mark.parametrize("n_act", [1, 64, 1024, 8192, 65536])
 def test_c2_full_size_sampled(nb, n_act):
