@@ -139,6 +139,35 @@ def test_batch_alone_and_mixed_are_bitwise_equal(nb, precision):
     assert sum(b1.energy(j1, t_end)) == sum(b2.energy(j2, t_end))
 
 
+def test_batch_job_at_a_high_pool_offset(nb):
+    """A job placed after 2^25 + 123 parked bodies (its records start 2.7 GB into the
+    record array, so byte offsets pass 2^31) takes the same block steps, bitwise, as
+    in a pool of its own. The parked job is given as a state already at its end
+    time, so it never steps and needs no start-up."""
+    t_end = 1 << (L - 2)
+    target = cluster(1000, 77)
+    b1 = make_batch(nb, 1000, 1)
+    j1 = b1.add(target.m, target.x, target.v, t_end)
+    run_to_end(b1)
+    alone = states(b1, [j1])[j1]
+    b1.close()
+    big = (1 << 25) + 123
+    say("parked bodies", big)
+    b2 = make_batch(nb, big + 1000, 2)
+    g = ni.rng(78)
+    park = b2.add(np.full(big, 1.0 / big), g.normal(0, 1, (3, big)), np.zeros((3, big)), 0,
+                  tick=np.zeros(big, np.int64), level=np.zeros(big, np.int32))
+    j2 = b2.add(target.m, target.x, target.v, t_end)
+    assert b2.info(j2)[0] == big
+    steps, _, _ = run_to_end(b2)
+    assert steps > 10
+    high = states(b2, [j2])[j2]
+    for k in alone:
+        assert np.array_equal(alone[k], high[k]), k
+    assert b2.info(park) == (0, big)
+    b2.close()
+
+
 # ------------------------------------------------------------- admission ------
 def test_batch_admission_remove_and_reuse(nb):
     b = make_batch(nb, 1000, 3)
