@@ -48,10 +48,10 @@ KERNEL_SRCS = [os.path.join(ROOT, "paper_1812_00367_amd", "csrc", f)
 # profiles/eval_fp64_plummer65536.md, keyed by the sha256 prefix of those sources (a
 # key is moved to a new hash only when the evaluation kernels' gfx950 assembly is
 # unchanged).
-TRAFFIC = {"db1f44bac1900e3c": {"fp64": 2.00 * 21978 * 1024 + 81920 * 1024}}
+TRAFFIC = {"19f9c23fbeb8fc9a": {"fp64": 2.00 * 21978 * 1024 + 81920 * 1024}}
 # Flops per interaction the evaluation kernels execute (SQ_INSTS_VALU_FLOPS_FP64 /
 # _FP32 x 64 lanes / N^2, same profile), keyed the same way.
-EXECUTED_FLOPS = {"db1f44bac1900e3c": {"fp64": 88.0, "split": 86.0}}
+EXECUTED_FLOPS = {"19f9c23fbeb8fc9a": {"fp64": 88.0, "split": 86.0}}
 
 
 def kernel_sources_hash():

@@ -139,7 +139,9 @@ nb_status nb_get_state(nb_ctx *ctx, const nb_state *dst);
 
 /* Hermite start-up on a synchronised state: two evaluations of every body (the
  * first gives a and j, the second s with the predicted accelerations set to the
- * first a), c = 0, then the initial-step rule for every body. Asynchronous. */
+ * first a), c = 0, then the initial-step rule for every body. Asynchronous; a
+ * non-finite result (e.g. two bodies at one place with eps = 0) is reported by the
+ * next waiting call as NB_ERR_NUMERIC. */
 nb_status nb_start(nb_ctx *ctx);
 
 /* Block-step selection: tick_next = min over bodies of (tick + step) and the
@@ -299,7 +301,7 @@ nb_status nb_batch_remove(nb_batch *b, int32_t job);
  * Host outputs indexed by job id (arrays of max_jobs entries, each may be NULL):
  * the number of bodies the job advanced (0: finished, failed or not present), its
  * next block time (a finished or failed job keeps the last one computed), and its
- * error word (0 ok; 1 a non-finite corrector value;
+ * error word (0 ok; 1 a non-finite start-up evaluation or corrector value;
  * 2 a body needs a step below dt_min; 3 an inconsistent time or level). A job with
  * a non-zero error word is not stepped again; the other jobs are unaffected.
  * *h_interactions = the sum over jobs of n_act x n. */

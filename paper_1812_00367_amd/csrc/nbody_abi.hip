@@ -143,7 +143,7 @@ nb_status sync_status(nb_ctx *c)
             s = fail(c, NB_ERR_ARG, "a body's time or level is inconsistent with the call "
                                     "(level outside [0, L], or a body ahead of the target time)");
         else if (e[nb::kErrNumeric])
-            s = fail(c, NB_ERR_NUMERIC, "the corrector produced a non-finite value");
+            s = fail(c, NB_ERR_NUMERIC, "a non-finite value (start-up evaluation or corrector)");
         else
             s = fail(c, NB_ERR_NUMERIC, "a body needs a step below 2^dt_min_log2");
         NB_HIP(c, nb::launch_fill_i32(c->A.status->err, 0, nb::kErrWords, c->st));

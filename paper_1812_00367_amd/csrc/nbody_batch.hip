@@ -1018,6 +1018,12 @@ __global__ __launch_bounds__(256) void k_bfinish(Pool P, int64_t cap, int mode, 
             P.a5n[i] = 0.0;
             P.phi[i] = ev[9];
             init = 1;
+            bool finite = true;
+#pragma unroll
+            for (int c = 0; c < 10; ++c)
+                finite = finite && isfinite(ev[c]);
+            if (!finite)  // e.g. two bodies at one place without softening
+                P.j_err[job] = kJobNumeric;
         } else {
             const int64_t tn = P.j_tnext[job], ti = P.tick[i];
             if (ti >= tn) {

@@ -123,6 +123,7 @@ __global__ __launch_bounds__(256) void k_start_store(Arrays A, int n)
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n)
         return;
+    bool finite = true;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
         const size_t e = (size_t)k * n + i;
@@ -130,10 +131,14 @@ __global__ __launch_bounds__(256) void k_start_store(Arrays A, int n)
         A.j[e] = A.evalbuf[(size_t)(3 + k) * n + i];
         A.s[e] = A.evalbuf[(size_t)(6 + k) * n + i];
         A.c[e] = 0.0;
+        finite = finite && isfinite(A.a[e]) && isfinite(A.j[e]) && isfinite(A.s[e]);
     }
     A.phi[i] = A.evalbuf[(size_t)9 * n + i];
     A.a4n[i] = 0.0;
     A.a5n[i] = 0.0;
+    // (e.g. two bodies at one place without softening)
+    if (!finite || !isfinite(A.phi[i]))
+        raise_err(A.status, kErrNumeric);
 }
 
 // --------------------------------------------------------- pairwise (FP64) ----

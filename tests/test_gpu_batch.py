@@ -168,6 +168,23 @@ def test_batch_job_at_a_high_pool_offset(nb):
     b2.close()
 
 
+def test_batch_coincident_bodies_without_softening(nb):
+    """A job with two bodies at one place and eps = 0 has a non-finite start-up: its
+    error word says so (1) and it never steps; a good job beside it is unaffected."""
+    m = np.array([0.4, 0.35, 0.25])
+    x = np.array([[0.1, 0.1, -0.6], [0.2, 0.2, 0.3], [0.0, 0.0, 0.1]])
+    v = np.array([[0.0, 0.3, 0.1], [0.1, 0.0, -0.2], [0.0, 0.0, 0.05]])
+    good = cluster(200, 31)
+    t_end = 1 << (L - 3)
+    b = make_batch(nb, 203, 2, eps=0.0)
+    jb = b.add(m, x, v, t_end)
+    jg = b.add(good.m, good.x, good.v, t_end)
+    nact, tnext, err, _ = b.step()
+    assert err[jb] == 1 and nact[jb] == 0
+    assert err[jg] == 0 and nact[jg] > 0
+    b.close()
+
+
 # ------------------------------------------------------------- admission ------
 def test_batch_admission_remove_and_reuse(nb):
     b = make_batch(nb, 1000, 3)

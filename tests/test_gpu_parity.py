@@ -167,6 +167,28 @@ def test_eval_tiny_systems(nb):
     assert np.allclose(got, ref, rtol=1e-14, atol=1e-300)
 
 
+def test_coincident_bodies(nb):
+    """Two bodies at the same place: with softening every term is finite and matches
+    the oracle; without it their pair term is not finite, and the first block step
+    reports NB_ERR_NUMERIC instead of carrying non-finite values on."""
+    m = np.array([0.4, 0.35, 0.25])
+    x = np.array([[0.1, 0.1, -0.6], [0.2, 0.2, 0.3], [0.0, 0.0, 0.1]])
+    v = np.array([[0.0, 0.3, 0.1], [0.1, 0.0, -0.2], [0.0, 0.0, 0.05]])
+    sim = make_sim(nb, 3, eps=1e-2)
+    sim.set_state(m, x, v)
+    sim.predict(0)
+    got = host(sim.evaluate(np.arange(3, dtype=np.int32)))
+    ref = oracle.evaluate(m, x, v, np.zeros((3, 3)), 1e-2)
+    assert np.isfinite(got).all()
+    assert max(eval_errors(got, ref)) <= TOL_EVAL
+    sim0 = make_sim(nb, 3, eps=0.0)
+    sim0.set_state(m, x, v)
+    sim0.start()
+    with pytest.raises(nb.NBodyError) as e:
+        sim0.step()   # its first wait reports the start-up's non-finite values
+    assert e.value.status == 5 and "non-finite" in str(e.value), str(e.value)
+
+
 def test_eval_empty_active_set_is_noop(nb):
     n = 100
     ic, ap = system(n, 7)
