@@ -21,8 +21,9 @@
 namespace nb {
 namespace {
 
-constexpr int kCrkTile = 128;     // j-records per LDS tile
-constexpr int kCrkWaves = 4;      // waves per workgroup, one active body per lane
+constexpr int kCrkTile = 256;     // j-records per LDS tile
+constexpr int kCrkWaves = 4;      // waves per workgroup
+constexpr int kCrkIPL = 2;        // active bodies per lane
 constexpr int kCrkBS = 64 * kCrkWaves;
 constexpr int kCrkComp = 13;      // a(3) j(3) s(3) c(3) phi
 
@@ -109,33 +110,39 @@ __device__ __forceinline__ void interact_crackle(ICrk &b, const double2 p0, cons
     b.acc[12] -= mr;
 }
 
-// One active body per lane; grid (ceil(n_act / 256), S); split s sweeps the
-// j-range [s jch, min(n, (s+1) jch)) in LDS tiles and writes its partial sums to
+// Two active bodies per lane (slots q and q + 256 of the workgroup's 512); grid
+// (ceil(n_act / 512), S); split s sweeps the j-range [s jch, min(n, (s+1) jch)) in
+// LDS tiles, each record read once for both bodies, and writes its partial sums to
 // part[(s * 13 + c) * n_act + q] (or straight to out when S = 1).
 __global__ __launch_bounds__(kCrkBS) void k_eval_crackle(Arrays A, int n, const int32_t *__restrict__ idx,
                                                          int n_act, double eps2, int jch, double *__restrict__ dst)
 {
     __shared__ double2 lds[kCrkTile * 7];
     const int tid = threadIdx.x;
-    const int q = blockIdx.x * kCrkBS + tid;
     const int sp = blockIdx.y;
-    int i = idx[q < n_act ? q : n_act - 1];
-    i = (i < 0 || i >= n) ? 0 : i;  // indices are checked on the host
-    ICrk b;
-    {
+    ICrk b[kCrkIPL];
+    int lo = 0x7fffffff, hi = -1;
+#pragma unroll
+    for (int u = 0; u < kCrkIPL; ++u) {
+        const int q = blockIdx.x * kCrkBS * kCrkIPL + u * kCrkBS + tid;
+        int i = idx[q < n_act ? q : n_act - 1];
+        i = (i < 0 || i >= n) ? 0 : i;  // indices are checked on the host
         const double2 *r = reinterpret_cast<const double2 *>(A.jrec + (size_t)i * kRecD);
         const double2 *rj = reinterpret_cast<const double2 *>(A.jrecj + (size_t)i * 4);
         const double2 r0 = r[0], r1 = r[1], r2 = r[2], r3 = r[3], r4 = r[4], j0 = rj[0], j1 = rj[1];
-        b.x[0] = r0.x; b.x[1] = r0.y; b.x[2] = r1.x;
-        b.v[0] = r1.y; b.v[1] = r2.x; b.v[2] = r2.y;
-        b.a[0] = r3.x; b.a[1] = r3.y; b.a[2] = r4.x;
-        b.j[0] = j0.x; b.j[1] = j0.y; b.j[2] = j1.x;
+        b[u].x[0] = r0.x; b[u].x[1] = r0.y; b[u].x[2] = r1.x;
+        b[u].v[0] = r1.y; b[u].v[1] = r2.x; b[u].v[2] = r2.y;
+        b[u].a[0] = r3.x; b[u].a[1] = r3.y; b[u].a[2] = r4.x;
+        b[u].j[0] = j0.x; b[u].j[1] = j0.y; b[u].j[2] = j1.x;
 #pragma unroll
         for (int c = 0; c < kCrkComp; ++c)
-            b.acc[c] = 0.0;
-        b.self = i;
+            b[u].acc[c] = 0.0;
+        b[u].self = i;
+        lo = min(lo, i);
+        hi = max(hi, i);
     }
-    const int lo = wave_min_i32(i), hi = wave_max_i32(i);
+    lo = wave_min_i32(lo);
+    hi = wave_max_i32(hi);
     const int jbeg = sp * jch;
     const int jend = min(n, jbeg + jch);
     const double2 *src = reinterpret_cast<const double2 *>(A.jrec);
@@ -156,20 +163,30 @@ __global__ __launch_bounds__(kCrkBS) void k_eval_crackle(Arrays A, int n, const 
         if (hi < j0 || lo >= j0 + kCrkTile) {
             for (int r = 0; r < kCrkTile; ++r) {
                 const double2 *L = lds + r * 7;
-                interact_crackle<false>(b, L[0], L[1], L[2], L[3], L[4], L[5], L[6], eps2, 0);
+                const double2 p0 = L[0], p1 = L[1], p2 = L[2], p3 = L[3], p4 = L[4], p5 = L[5], p6 = L[6];
+#pragma unroll
+                for (int u = 0; u < kCrkIPL; ++u)
+                    interact_crackle<false>(b[u], p0, p1, p2, p3, p4, p5, p6, eps2, 0);
             }
         } else {
             for (int r = 0; r < kCrkTile; ++r) {
                 const double2 *L = lds + r * 7;
-                interact_crackle<true>(b, L[0], L[1], L[2], L[3], L[4], L[5], L[6], eps2, j0 + r);
+                const double2 p0 = L[0], p1 = L[1], p2 = L[2], p3 = L[3], p4 = L[4], p5 = L[5], p6 = L[6];
+#pragma unroll
+                for (int u = 0; u < kCrkIPL; ++u)
+                    interact_crackle<true>(b[u], p0, p1, p2, p3, p4, p5, p6, eps2, j0 + r);
             }
         }
         __syncthreads();
     }
-    if (q < n_act)
 #pragma unroll
-        for (int c = 0; c < kCrkComp; ++c)
-            dst[((size_t)sp * kCrkComp + c) * n_act + q] = b.acc[c];
+    for (int u = 0; u < kCrkIPL; ++u) {
+        const int q = blockIdx.x * kCrkBS * kCrkIPL + u * kCrkBS + tid;
+        if (q < n_act)
+#pragma unroll
+            for (int c = 0; c < kCrkComp; ++c)
+                dst[((size_t)sp * kCrkComp + c) * n_act + q] = b[u].acc[c];
+    }
 }
 
 // out[e] = sum over s of part[s * count + e], s ascending.
@@ -208,7 +225,7 @@ hipError_t launch_eval_crackle(const Arrays &A, int64_t n, const int32_t *idx, i
     if (n_act == 0)
         return hipGetLastError();
     // j-splits for about 4096 waves, within the partial buffer (10 doubles per slot)
-    const int64_t iblocks = (n_act + kCrkBS - 1) / kCrkBS;
+    const int64_t iblocks = (n_act + kCrkBS * kCrkIPL - 1) / (kCrkBS * kCrkIPL);
     int64_t S = (4096 + 4 * iblocks - 1) / (4 * iblocks);
     const int64_t tiles = (n + kCrkTile - 1) / kCrkTile;
     S = S < tiles ? S : tiles;
