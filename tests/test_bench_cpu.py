@@ -1,4 +1,4 @@
-"""Host checks of the benchmark driver (no GPU)."""
+"""Host checks of the benchmark script (no GPU)."""
 import os
 import subprocess
 import sys
