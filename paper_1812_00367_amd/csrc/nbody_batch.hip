@@ -76,6 +76,11 @@ struct Pool {
     int64_t *j_off, *j_n, *j_tend;
     int64_t *j_nact, *j_tnext;
     int32_t *j_err;
+    // the next block time without a scan: the smallest t + dt of the bodies not due
+    // in the job's last step (unchanged by it) and of its due bodies after their
+    // correction; j_mok = 1 when both are up to date
+    int64_t *j_mrest, *j_mact;
+    int32_t *j_mok;
     // plan (by position among the stepping jobs)
     int32_t *pl_job, *pl_na, *pl_S, *pl_tiles, *pl_jch, *pl_wide;
     int64_t *pl_item0[kClasses], *pl_act0, *pl_pbase;
@@ -91,6 +96,10 @@ struct Pool {
 constexpr int kBS = 1024;
 constexpr int kBW = kBS / 64;
 constexpr int kUnroll = 8;  // bodies per thread per round of the active-set scans
+// Jobs larger than one round of the minimum scan take their next block time from the
+// previous step instead (smaller ones scan: the bookkeeping would cost more than the
+// round it saves).
+constexpr int64_t kKnownMinN = (int64_t)kUnroll * kBS;
 
 __global__ __launch_bounds__(kBS) void k_bact(Pool P, const int32_t *__restrict__ jobs, int L)
 {
@@ -109,8 +118,12 @@ __global__ __launch_bounds__(kBS) void k_bact(Pool P, const int32_t *__restrict_
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     int64_t mn = INT64_MAX;
     int badlevel = 0;
+    // after a step of this job, t_next = min(t + dt) over its bodies is known without a
+    // scan: the bodies that were not due kept their t and dt, and the due ones were
+    // reduced by the finishing pass (the first step after admission scans)
+    const bool known = P.j_mok[job] != 0;
     // kUnroll bodies per thread per round, their loads issued together
-    for (int64_t k0 = threadIdx.x; k0 < n; k0 += kUnroll * kBS) {
+    for (int64_t k0 = threadIdx.x; !known && k0 < n; k0 += kUnroll * kBS) {
         int lv[kUnroll];
         int64_t tk[kUnroll];
 #pragma unroll
@@ -145,9 +158,14 @@ __global__ __launch_bounds__(kBS) void k_bact(Pool P, const int32_t *__restrict_
         tn = red[w] < tn ? red[w] : tn;
         anybad |= sbad[w];
     }
+    if (known) {
+        const int64_t r = P.j_mrest[job], a = P.j_mact[job];
+        tn = r < a ? r : a;
+    }
     const int err0 = P.j_err[job];  // not written by this kernel before its end
     const bool skip = tn > P.j_tend[job] || err0 != kJobOk || anybad;
     int64_t base = 0;
+    int64_t rest = INT64_MAX;  // smallest t + dt of the bodies not due at tn
     if (!skip) {
         // super-rounds of kUnroll chunks of kBS bodies: loads issued together, one
         // barrier pair per super-round; chunk u of a super-round starts after the due
@@ -161,7 +179,10 @@ __global__ __launch_bounds__(kBS) void k_bact(Pool P, const int32_t *__restrict_
                 int lv = k < n ? P.level[off + k] : 0;
                 const int64_t tk = k < n ? P.tick[off + k] : 0;
                 lv = (lv < 0 || lv > L) ? L : lv;
-                due[u] = k < n && tk + ((int64_t)1 << (L - lv)) == tn;
+                const int64_t e = tk + ((int64_t)1 << (L - lv));
+                due[u] = k < n && e == tn;
+                if (k < n && !due[u])
+                    rest = e < rest ? e : rest;
             }
 #pragma unroll
             for (int u = 0; u < kUnroll; ++u) {
@@ -186,11 +207,27 @@ __global__ __launch_bounds__(kBS) void k_bact(Pool P, const int32_t *__restrict_
             __syncthreads();
         }
     }
+    const bool keep = !skip && n > kKnownMinN;  // the same in every thread
+    if (keep) {
+        rest = wave_min_i64(rest);
+        __syncthreads();  // red[] is reused
+        if (lane == 0)
+            red[wave] = rest;
+        __syncthreads();
+        if (threadIdx.x == 0)
+            for (int w = 0; w < kBW; ++w)
+                rest = red[w] < rest ? red[w] : rest;
+    }
     if (threadIdx.x == 0) {
         P.j_tnext[job] = tn;
         P.j_nact[job] = skip ? 0 : base;
         if (anybad)
             P.j_err[job] = kJobLevel;
+        // for the next step: the bodies not due now keep their t + dt; the finishing
+        // pass lowers j_mact to the due bodies' new t + dt
+        P.j_mrest[job] = rest;
+        P.j_mact[job] = INT64_MAX;
+        P.j_mok[job] = keep ? 1 : 0;
     }
 }
 
@@ -994,54 +1031,76 @@ __global__ __launch_bounds__(256) void k_bfinish(Pool P, int64_t cap, int mode, 
 #pragma unroll
             for (int c = 0; c < 10; ++c)
                 ev[c] += __shfl_xor(ev[c], o, 64);
-        if (!live || l != 0)
-            continue;
-        const int64_t off = P.j_off[job];
-        const int64_t i = P.act[off + slot];
-        if (mode == kStartA) {
-            for (int c = 0; c < 3; ++c) {
-                P.jrec[i * kRecD + 6 + c] = ev[c];
-                if (P.jrec32)
-                    P.jrec32[i * kRecF + 12 + c] = (float)ev[c];
+        int64_t nxt = INT64_MAX;  // the body's new t + dt (a completed step only)
+        do {
+            if (!live || l != 0)
+                break;
+            const int64_t off = P.j_off[job];
+            const int64_t i = P.act[off + slot];
+            if (mode == kStartA) {
+                for (int c = 0; c < 3; ++c) {
+                    P.jrec[i * kRecD + 6 + c] = ev[c];
+                    if (P.jrec32)
+                        P.jrec32[i * kRecF + 12 + c] = (float)ev[c];
+                }
+                break;
             }
-            continue;
-        }
-        int init = 0;
-        if (mode == kStartB) {
-            for (int c = 0; c < 3; ++c) {
-                P.a[c * cap + i] = ev[0 + c];
-                P.j[c * cap + i] = ev[3 + c];
-                P.s[c * cap + i] = ev[6 + c];
-                P.c[c * cap + i] = 0.0;
-            }
-            P.a4n[i] = 0.0;
-            P.a5n[i] = 0.0;
-            P.phi[i] = ev[9];
-            init = 1;
-            bool finite = true;
+            int init = 0;
+            if (mode == kStartB) {
+                for (int c = 0; c < 3; ++c) {
+                    P.a[c * cap + i] = ev[0 + c];
+                    P.j[c * cap + i] = ev[3 + c];
+                    P.s[c * cap + i] = ev[6 + c];
+                    P.c[c * cap + i] = 0.0;
+                }
+                P.a4n[i] = 0.0;
+                P.a5n[i] = 0.0;
+                P.phi[i] = ev[9];
+                init = 1;
+                bool finite = true;
 #pragma unroll
-            for (int c = 0; c < 10; ++c)
-                finite = finite && isfinite(ev[c]);
-            if (!finite)  // e.g. two bodies at one place without softening
-                P.j_err[job] = kJobNumeric;
-        } else {
-            const int64_t tn = P.j_tnext[job], ti = P.tick[i];
-            if (ti >= tn) {
-                P.j_err[job] = kJobLevel;
-                continue;
+                for (int c = 0; c < 10; ++c)
+                    finite = finite && isfinite(ev[c]);
+                if (!finite)  // e.g. two bodies at one place without softening
+                    P.j_err[job] = kJobNumeric;
+            } else {
+                const int64_t tn = P.j_tnext[job], ti = P.tick[i];
+                if (ti >= tn) {
+                    P.j_err[job] = kJobLevel;
+                    break;
+                }
+                const bool ok = correct_body(P.x, P.v, P.a, P.j, P.s, P.c, P.a4n, P.a5n, (size_t)cap,
+                                             (size_t)i, ev, 1, (double)(tn - ti) * tick_size);
+                P.phi[i] = ev[9];
+                P.tick[i] = tn;
+                if (!ok)
+                    P.j_err[job] = kJobNumeric;
             }
-            const bool ok = correct_body(P.x, P.v, P.a, P.j, P.s, P.c, P.a4n, P.a5n, (size_t)cap,
-                                         (size_t)i, ev, 1, (double)(tn - ti) * tick_size);
-            P.phi[i] = ev[9];
-            P.tick[i] = tn;
-            if (!ok)
-                P.j_err[job] = kJobNumeric;
+            bool dtmin;
+            const int lv = level_for_body(P.a, P.j, P.s, P.c, P.a4n, P.a5n, (size_t)cap, (size_t)i,
+                                          P.tick[i], P.level[i], init, eta, eta_init, dt_max_log2, L,
+                                          &dtmin);
+            P.level[i] = lv;
+            if (dtmin)
+                P.j_err[job] = kJobDtMin;
+            if (mode == kStep && P.j_n[job] > kKnownMinN)
+                nxt = P.tick[i] + ((int64_t)1 << (L - lv));
+        } while (false);
+        if (mode == kStep) {
+            // the due bodies' new t + dt, reduced per job for the next active-set
+            // pass: a job's bodies are contiguous in plan order, so each job present
+            // in the wave takes one wave minimum and one atomic
+            unsigned long long todo = __ballot(nxt != INT64_MAX);
+            while (todo) {
+                const int lead = __builtin_ctzll(todo);
+                const int jb = __shfl(job, lead, 64);
+                const bool mine = nxt != INT64_MAX && job == jb;
+                const int64_t m = wave_min_i64(mine ? nxt : INT64_MAX);
+                if (lane == lead)
+                    atomicMin(reinterpret_cast<unsigned long long *>(P.j_mact + jb), (unsigned long long)m);
+                todo &= ~__ballot(mine);
+            }
         }
-        bool dtmin;
-        P.level[i] = level_for_body(P.a, P.j, P.s, P.c, P.a4n, P.a5n, (size_t)cap, (size_t)i, P.tick[i],
-                                    P.level[i], init, eta, eta_init, dt_max_log2, L, &dtmin);
-        if (dtmin)
-            P.j_err[job] = kJobDtMin;
     }
 }
 
@@ -1056,6 +1115,7 @@ __global__ __launch_bounds__(256) void k_bjob_init(Pool P, int job, int64_t off,
         P.j_nact[job] = n;
         P.j_tnext[job] = tick0;
         P.j_err[job] = kJobOk;
+        P.j_mok[job] = 0;  // the first step scans
     }
     if (k < n)
         P.act[off + k] = (int32_t)(off + k);
@@ -1255,6 +1315,9 @@ size_t b_layout(const nb_batch_params *p, Pool *P, int32_t **d_jobs, int32_t **d
     P->j_nact = (int64_t *)blk;
     P->j_tnext = blk ? (int64_t *)(blk + 8 * J) : nullptr;
     P->j_err = blk ? (int32_t *)(blk + 16 * J) : nullptr;
+    P->j_mrest = (int64_t *)take(8 * J);
+    P->j_mact = (int64_t *)take(8 * J);
+    P->j_mok = (int32_t *)take(4 * J);
     P->pl_job = (int32_t *)take(4 * J);
     P->pl_na = (int32_t *)take(4 * J);
     P->pl_S = (int32_t *)take(4 * J);
