@@ -372,10 +372,11 @@ def test_batch_split_startup_within_rounding_bound(nb):
 # ------------------------------------------ active sets of jobs over 8192 bodies --
 def test_batch_active_sets_of_large_jobs(nb):
     """Jobs of 9000 and 17001 bodies (the active-set scan takes 8192 bodies per round:
-    two and three rounds, the last ragged) beside a small one: after every batch step
-    the bodies that advanced are exactly the oracle's active set computed from the
-    job's times and levels before the step, and the reported count and block time
-    match it."""
+    two and three rounds, the last ragged; after their first step both take the next
+    block time from the previous step's minima instead of a scan) beside a small one:
+    after every batch step the bodies that advanced are exactly the oracle's active
+    set computed from the job's times and levels before the step, and the reported
+    count and block time match it."""
     sizes = [9000, 300, 17001]
     b = make_batch(nb, sum(sizes), 3)
     jobs = []
