@@ -82,7 +82,8 @@ struct Pool {
     int64_t *j_mrest, *j_mact;
     int32_t *j_mok;
     // plan (by position among the stepping jobs)
-    int32_t *pl_job, *pl_na, *pl_S, *pl_tiles, *pl_jch, *pl_wide;
+    int32_t *pl_job, *pl_na, *pl_S, *pl_tiles, *pl_jch;
+    int32_t *pl_keep;   // 1: the job keeps its running minima (more than kKnownMinN bodies)
     int64_t *pl_item0[kClasses], *pl_act0, *pl_pbase;
     StepHdr *hdr;
     double *en_bsum;
@@ -399,7 +400,7 @@ __device__ __forceinline__ void plan_jobs(const Pool &P, const int32_t *__restri
             P.pl_S[q] = (int32_t)sp.S;
             P.pl_tiles[q] = (int32_t)sp.tiles;
             P.pl_jch[q] = (int32_t)sp.jch;
-            P.pl_wide[q] = sp.wide ? 1 : 0;
+            P.pl_keep[q] = n > kKnownMinN ? 1 : 0;
             for (int k = 0; k < kClasses; ++k)
                 P.pl_item0[k][q] = c_it[k] + x_it[k];
             P.pl_act0[q] = c_act + x_act;
@@ -998,6 +999,7 @@ __global__ __launch_bounds__(256) void k_bfinish(Pool P, int64_t cap, int mode, 
         const int job = P.pl_job[q];
         const int64_t slot = (live ? e : total - 1) - act0[q], na = P.pl_na[q], pbase = P.pl_pbase[q];
         const int S = P.pl_S[q];
+        const bool keep = P.pl_keep[q] != 0;
         double ev[10];
 #pragma unroll
         for (int c = 0; c < 10; ++c)
@@ -1083,7 +1085,7 @@ __global__ __launch_bounds__(256) void k_bfinish(Pool P, int64_t cap, int mode, 
             P.level[i] = lv;
             if (dtmin)
                 P.j_err[job] = kJobDtMin;
-            if (mode == kStep && P.j_n[job] > kKnownMinN)
+            if (mode == kStep && keep)
                 nxt = P.tick[i] + ((int64_t)1 << (L - lv));
         } while (false);
         if (mode == kStep) {
@@ -1325,7 +1327,7 @@ size_t b_layout(const nb_batch_params *p, Pool *P, int32_t **d_jobs, int32_t **d
     P->pl_jch = (int32_t *)take(4 * J);
     for (int k = 0; k < nb::kClasses; ++k)
         P->pl_item0[k] = (int64_t *)take(8 * J);
-    P->pl_wide = (int32_t *)take(4 * J);
+    P->pl_keep = (int32_t *)take(4 * J);
     P->pl_act0 = (int64_t *)take(8 * J);
     P->pl_pbase = (int64_t *)take(8 * J);
     P->hdr = (nb::StepHdr *)take(sizeof(nb::StepHdr));
