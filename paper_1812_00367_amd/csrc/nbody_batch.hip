@@ -1004,9 +1004,24 @@ __global__ __launch_bounds__(256) void k_bfinish(Pool P, int64_t cap, int mode, 
 #pragma unroll
         for (int c = 0; c < 10; ++c)
             ev[c] = 0.0;
-        // chunks l, l + 4, ... in ascending order; four of them are loaded at once so
-        // their round trips overlap (the additions keep the one-by-one order)
+        // chunks l, l + 4, ... in ascending order; eight (then four) of them are loaded
+        // at once so their round trips overlap (the additions keep the one-by-one order)
         int sp = l;
+        for (; sp + 7 * kFinLanes < S; sp += 8 * kFinLanes) {
+            double t[8][10];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const double *src = P.part + pbase + (int64_t)(sp + u * kFinLanes) * 10 * na + slot;
+#pragma unroll
+                for (int c = 0; c < 10; ++c)
+                    t[u][c] = src[(int64_t)c * na];
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+#pragma unroll
+                for (int c = 0; c < 10; ++c)
+                    ev[c] += t[u][c];
+        }
         for (; sp + 3 * kFinLanes < S; sp += 4 * kFinLanes) {
             double t[4][10];
 #pragma unroll
