@@ -287,6 +287,30 @@ def test_batch_failing_job_is_isolated(nb):
 
 
 # ------------------------------------------------------ multi-step calls ------
+def test_run_steps_on_the_null_stream(nb):
+    """The null stream cannot be captured, so there nb_batch_run launches every step
+    directly; the states are bitwise those of the captured graphs on a stream of the
+    batch's own."""
+    ics = [cluster(n, 40 + n) for n in (700, 90)]
+    t_end = 1 << L
+    out = []
+    for stream in (None, torch.cuda.default_stream()):
+        b = make_batch(nb, 790, 2, stream=stream)
+        jobs = [b.add(ic.m, ic.x, ic.v, t_end) for ic in ics]
+        steps = 0
+        while True:
+            *_, taken = b.run_steps(16)
+            steps += taken
+            if taken < 16:
+                break
+        out.append((steps, states(b, jobs)))
+        b.close()
+    assert out[0][0] == out[1][0] > 16
+    for j in out[0][1]:
+        for k in out[0][1][j]:
+            assert np.array_equal(out[0][1][j][k], out[1][1][j][k]), (j, k)
+
+
 def test_run_steps_equals_single_steps(nb):
     """nb_batch_run (many steps, one wait) gives bitwise the states of the same number
     of nb_batch_step calls, and counts the same interactions."""
