@@ -153,3 +153,18 @@ def test_crackle_start_block_steps_match_oracle(nb):
     assert np.array_equal(np.array([t for t, _ in log]), ostt)
     assert np.array_equal(np.array([k for _, k in log]), osna)
     assert np.abs(st["x"] - ost.x).max() < 1e-9
+
+
+def test_crackle_is_fp64_in_a_split_precision_context(nb):
+    """The crackle evaluation reads only the FP64 records, so a context whose plain
+    evaluation is split precision gives bitwise the same crackle output."""
+    n, n_act = 1500, 700
+    ic, a, j, s, c = state(n, 71)
+    outs = []
+    for prec in (nb.NB_FP64, nb.NB_SPLIT):
+        sim = nb.Simulation(n, eps=1e-4, dt_max_log2=DT_MAX, dt_min_log2=DT_MIN, precision=prec)
+        sim.set_state(ic.m, ic.x, ic.v, a=a, j=j, s=s, c=c, tick=np.zeros(n, np.int64),
+                      level=np.zeros(n, np.int32))
+        sim.predict(0)
+        outs.append(host(sim.evaluate_crackle(ni.active_subset(n, n_act, 72))))
+    assert np.array_equal(outs[0], outs[1])
