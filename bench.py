@@ -506,10 +506,11 @@ def ensemble_workload(count=512, t_end=0.25, jchunk=0, precisions=("fp64", "spli
     return res
 
 
-# Work items per job of the serving batch: twice the library default, which gives the
-# large, sparse serving jobs more parallel items (measured 7-9 % lower p50 latency at
-# 3 requests/s) for a larger partial-sum buffer inside the same HBM budget.
-SERVE_ITEMS_PER_JOB = 4096
+# Work items per job of the serving batch: four times the library default, which gives
+# the large, sparse serving jobs more parallel items for a larger partial-sum buffer
+# inside the same HBM budget (at 3 requests/s, interleaved: p50 1.94 s against 1.99 s
+# with 4096 items and 2.19 s with 2048; 16384 items, 2.00-2.02 s, leave less pool).
+SERVE_ITEMS_PER_JOB = 8192
 
 
 def serving_workload(rates, count=24, budget_gib=32.0, slots=64, t_end=1.0, precision="fp64",
