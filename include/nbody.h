@@ -176,6 +176,36 @@ nb_status nb_evaluate(nb_ctx *ctx, const int32_t *d_idx, int64_t n_act, double *
  * idx as nb_evaluate. Does not feed nb_correct. Stream-ordered. */
 nb_status nb_evaluate_crackle(nb_ctx *c, const int32_t *d_idx, int64_t n_act, double *d_out);
 
+/* Size of the device memory nb_evaluate_static uses: a file-scope array that each
+ * GPU the library runs on holds until the process ends. */
+#define NB_STATIC_SCRATCH_BYTES ((size_t)128 << 20)
+
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid allocation): the evaluation of
+ * nb_evaluate (FP64) without a context or workspace. It allocates nothing: its
+ * j-records and partial sums live in the library's fixed device array of
+ * NB_STATIC_SCRATCH_BYTES bytes.
+ *   n bodies with masses d_m[n] and predicted positions, velocities and
+ *   accelerations d_xp, d_vp, d_ap ([3][n] component-major, device); softening
+ *   eps >= 0; the active bodies d_idx[n_act] (int32, device, each in [0, n)); the
+ *   result d_out[10][n_act] (device; the layout of nb_evaluate's output).
+ *   stream: hipStream_t, NULL = the null stream. Stream-ordered, returns without
+ *   waiting; every kernel it enqueues is a plain kernel launch (no memset), so the
+ *   call can be captured into a HIP graph.
+ * It takes the evaluation kernels with the launch shapes of nb_evaluate (default
+ * table and partial-sum capacity), so its result is bitwise that of nb_evaluate on
+ * a context of n bodies.
+ * Errors: NB_ERR_ARG for n outside [1, 2^30], n_act outside [0, n], eps < 0 or a
+ * NULL pointer; NB_ERR_SPACE (nothing enqueued) when the j-records (80 n bytes)
+ * plus the partial sums of the launch shape (80 S n_act bytes) do not fit the array;
+ * NB_ERR_DEVICE for a HIP error. It cannot wait for the device, so an index outside
+ * [0, n) is not returned as a status: every value of d_out is then NaN.
+ * Every call on one GPU shares that GPU's array: calls that overlap on one GPU
+ * (two streams, or two host threads) race and give undefined results. */
+nb_status nb_evaluate_static(int64_t n, const double *d_m, const double *d_xp, const double *d_vp,
+                             const double *d_ap, double eps, const int32_t *d_idx, int64_t n_act,
+                             double *d_out, void *stream);
+
 /* Supply the evaluation of the bodies d_idx from outside instead of nb_evaluate:
  * d_in[10][n_act] (same layout as nb_evaluate's output) becomes the result that
  * the next nb_correct with the same d_idx and n_act uses. This is how partial sums

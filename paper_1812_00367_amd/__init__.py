@@ -22,7 +22,7 @@ from . import _abi
 from ._abi import NB_FLAG_START_CRACKLE, NB_FP64, NB_SPLIT, NBodyError
 
 __all__ = ["Simulation", "Batch", "NBodyError", "NB_FP64", "NB_SPLIT", "NB_FLAG_START_CRACKLE",
-           "workspace_bytes",
+           "workspace_bytes", "evaluate_static",
            "batch_workspace_bytes"]
 
 
@@ -277,6 +277,30 @@ class Simulation:
             if record is not None:
                 record(tn, na)
         return steps, log, inter
+
+
+def evaluate_static(m, xp, vp, ap, eps, idx, out=None, stream=None):
+    """nb_evaluate_static: a, j, s, phi of the bodies idx against all n predicted bodies
+    (m[n], xp / vp / ap [3][n], float64 tensors on the GPU) without a context or
+    workspace; the library's fixed device array holds its intermediates. Returns
+    out[10][n_act]. Enqueued on `stream` (torch's current stream by default)."""
+    torch = _torch()
+    if not torch.cuda.is_available():
+        raise RuntimeError("paper_1812_00367_amd needs a ROCm GPU; none is visible")
+    lib = _abi.load()
+    n = int(m.shape[0])
+    idx = torch.as_tensor(idx, dtype=torch.int32, device=m.device).reshape(-1).contiguous()
+    n_act = int(idx.shape[0])
+    if out is None:
+        out = torch.empty((10, n_act), dtype=torch.float64, device=m.device)
+    if stream is None:
+        stream = torch.cuda.current_stream(m.device)
+    rc = lib.nb_evaluate_static(n, _ptr(m), _ptr(xp), _ptr(vp), _ptr(ap), float(eps), _ptr(idx),
+                                n_act, _ptr(out), ctypes.c_void_p(stream.cuda_stream))
+    if rc:
+        raise NBodyError(rc, "nb_evaluate_static failed (arguments, or more than "
+                             f"{_abi.NB_STATIC_SCRATCH_BYTES} bytes of device memory needed)")
+    return out
 
 
 from .batch import Batch, batch_workspace_bytes  # noqa: E402

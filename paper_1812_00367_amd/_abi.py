@@ -13,13 +13,14 @@ LIB_PATH = os.path.join(PKG, "libnbody.so")
 NB_OK, NB_ERR_ARG, NB_ERR_SPACE, NB_ERR_DEVICE, NB_ERR_STATE, NB_ERR_NUMERIC = range(6)
 NB_FP64, NB_SPLIT = 0, 1
 NB_FLAG_START_CRACKLE = 1
+NB_STATIC_SCRATCH_BYTES = 128 << 20
 STATUS_NAMES = {0: "NB_OK", 1: "NB_ERR_ARG", 2: "NB_ERR_SPACE", 3: "NB_ERR_DEVICE",
                 4: "NB_ERR_STATE", 5: "NB_ERR_NUMERIC"}
 
 # Every function the header declares (checked against include/nbody.h by the tests).
 EXPORTS = ["nb_workspace_bytes", "nb_create", "nb_destroy", "nb_last_error", "nb_set_state",
            "nb_set_times", "nb_get_state", "nb_start", "nb_active", "nb_predict", "nb_get_predicted",
-           "nb_evaluate", "nb_evaluate_crackle", "nb_set_evaluation", "nb_eval_config", "nb_eval_table", "nb_correct", "nb_timesteps",
+           "nb_evaluate", "nb_evaluate_static", "nb_evaluate_crackle", "nb_set_evaluation", "nb_eval_config", "nb_eval_table", "nb_correct", "nb_timesteps",
            "nb_step", "nb_energy",
            "nb_batch_workspace_bytes", "nb_batch_create", "nb_batch_destroy", "nb_batch_last_error",
            "nb_batch_add", "nb_batch_remove", "nb_batch_step", "nb_batch_run", "nb_batch_get", "nb_batch_energy",
@@ -100,6 +101,7 @@ def load(path: str = LIB_PATH):
     lib.nb_predict.argtypes = [vp, i64]
     lib.nb_get_predicted.argtypes = [vp, vp, vp, vp]
     lib.nb_evaluate.argtypes = [vp, vp, i64, vp]
+    lib.nb_evaluate_static.argtypes = [i64, vp, vp, vp, vp, dbl, vp, i64, vp, vp]
     lib.nb_evaluate_crackle.argtypes = [vp, vp, i64, vp]
     lib.nb_set_evaluation.argtypes = [vp, vp, i64, vp]
     lib.nb_eval_config.argtypes = [vp, vp, i64, vp]

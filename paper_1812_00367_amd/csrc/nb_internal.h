@@ -74,6 +74,12 @@ hipError_t launch_predict(const Arrays &A, int64_t n, int64_t tick, int dt_min_l
 hipError_t launch_get_predicted(const Arrays &A, int64_t n, double *xp, double *vp, double *ap,
                                 hipStream_t st);
 hipError_t launch_copy_acc_to_jrec(const Arrays &A, int64_t n, bool split, hipStream_t st);
+// j-records of n bodies from predicted [3][n] arrays and masses.
+hipError_t launch_pack_records(const double *m, const double *xp, const double *vp,
+                               const double *ap, int64_t n, double *jrec, hipStream_t st);
+// out[0, count) = NaN if stt's index error word is set.
+hipError_t launch_poison_on_index_error(const Status *stt, double *out, int64_t count,
+                                        hipStream_t st);
 hipError_t launch_start_store(const Arrays &A, int64_t n, hipStream_t st);
 
 // One row of an evaluation launch table: the shape used for active sets of up to

@@ -9,6 +9,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <mutex>
 #include <new>
 
 using nb::Arrays;
@@ -264,6 +265,42 @@ EvalPlan plan_eval(int64_t n, int64_t n_act, int64_t partial_slots, bool split,
 
 }  // namespace nb
 
+namespace {
+
+// Device memory of nb_evaluate_static: one file-scope array per device (each GPU the
+// library runs on holds its own copy until the process ends). Host code never uses
+// the array's name as an address: the device address comes from hipGetSymbolAddress,
+// once per device, with that device current.
+static __device__ __align__(256) unsigned char scratch[NB_STATIC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices];
+
+// The device address of `scratch` on the current device (nullptr on failure).
+void *scratch_on_current_device(hipError_t *err)
+{
+    int dev = -1;
+    *err = hipGetDevice(&dev);
+    if (*err != hipSuccess)
+        return nullptr;
+    if (dev < 0 || dev >= kMaxDevices) {
+        *err = hipErrorInvalidDevice;
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        *err = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (*err != hipSuccess || !ptr)
+            return nullptr;
+        g_scratch_ptr[dev] = ptr;
+    }
+    return g_scratch_ptr[dev];
+}
+
+}  // namespace
+
 extern "C" {
 
 nb_status nb_workspace_bytes(const nb_params *p, size_t *h_bytes)
@@ -495,6 +532,50 @@ nb_status nb_evaluate_crackle(nb_ctx *c, const int32_t *d_idx, int64_t n_act, do
         return fail(c, NB_ERR_SPACE, "partial-sum buffer too small for %lld active bodies", (long long)n_act);
     NB_HIP(c, nb::launch_eval_crackle(c->A, c->p.n, d_idx, n_act, c->p.eps, partial_slots_of(&c->p),
                                       c->pred_tick, c->p.dt_min_log2, d_out, c->st));
+    return NB_OK;
+}
+
+nb_status nb_evaluate_static(int64_t n, const double *d_m, const double *d_xp, const double *d_vp,
+                             const double *d_ap, double eps, const int32_t *d_idx, int64_t n_act,
+                             double *d_out, void *stream)
+{
+    if (n < 1 || n > kMaxN || n_act < 0 || n_act > n || !(eps >= 0.0) || !isfinite(eps))
+        return NB_ERR_ARG;
+    if (n_act == 0)
+        return NB_OK;
+    if (!d_m || !d_xp || !d_vp || !d_ap || !d_idx || !d_out)
+        return NB_ERR_ARG;
+    // the launch shape nb_evaluate uses for a context of n bodies with the default
+    // partial-sum capacity and the built-in table, so both give the same bits
+    nb_params dp{};
+    dp.n = n;
+    dp.precision = NB_FP64;
+    const nb::EvalPlan P = nb::plan_eval(n, n_act, partial_slots_of(&dp), false, nullptr, 0);
+    const size_t rec_bytes = align256(80 * (size_t)n);
+    const size_t part_bytes = P.splits > 1 ? align256(80 * (size_t)P.splits * (size_t)n_act) : 0;
+    const size_t need = align256(sizeof(Status)) + rec_bytes + part_bytes;
+    if (need > NB_STATIC_SCRATCH_BYTES)
+        return NB_ERR_SPACE;
+    hipError_t e = hipSuccess;
+    char *base = (char *)scratch_on_current_device(&e);
+    if (!base)
+        return NB_ERR_DEVICE;
+    hipStream_t st = (hipStream_t)stream;
+    Arrays A{};
+    A.status = (Status *)base;
+    A.jrec = (double *)(base + align256(sizeof(Status)));
+    A.part = P.splits > 1 ? (double *)((char *)A.jrec + rec_bytes) : nullptr;
+    A.evalbuf = d_out;  // the kernels write (or reduce into) the caller's output
+    // the scratch keeps the last call's contents: clear the error words (a fill
+    // kernel, which graph capture records as a kernel node)
+    if ((e = nb::launch_fill_i32(A.status->err, 0, nb::kErrWords, st)) != hipSuccess)
+        return NB_ERR_DEVICE;
+    if ((e = nb::launch_pack_records(d_m, d_xp, d_vp, d_ap, n, A.jrec, st)) != hipSuccess)
+        return NB_ERR_DEVICE;
+    if ((e = nb::launch_eval(A, P, n, d_idx, n_act, eps, false, nullptr, st)) != hipSuccess)
+        return NB_ERR_DEVICE;
+    if ((e = nb::launch_poison_on_index_error(A.status, d_out, 10 * n_act, st)) != hipSuccess)
+        return NB_ERR_DEVICE;
     return NB_OK;
 }
 

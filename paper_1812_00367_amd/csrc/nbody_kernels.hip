@@ -99,6 +99,40 @@ __global__ __launch_bounds__(256) void k_get_predicted(const double *__restrict_
     }
 }
 
+// j-records {x, v, a, m} of n bodies from predicted [3][n] arrays (the layout
+// k_predict writes), for an evaluation of a state predicted elsewhere.
+__global__ __launch_bounds__(256) void k_pack_records(const double *__restrict__ m,
+                                                      const double *__restrict__ xp,
+                                                      const double *__restrict__ vp,
+                                                      const double *__restrict__ ap, int n,
+                                                      double *__restrict__ jrec)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n)
+        return;
+    const size_t s = (size_t)n;
+    double2 *r = reinterpret_cast<double2 *>(jrec + (size_t)i * kRecD);
+    r[0] = make_double2(xp[i], xp[s + i]);
+    r[1] = make_double2(xp[2 * s + i], vp[i]);
+    r[2] = make_double2(vp[s + i], vp[2 * s + i]);
+    r[3] = make_double2(ap[i], ap[s + i]);
+    r[4] = make_double2(ap[2 * s + i], m[i]);
+}
+
+// Every value of out[count] becomes NaN if the index check of an evaluation raised
+// its error word (for callers that cannot wait for the status block).
+__global__ __launch_bounds__(256) void k_poison_on_index_error(const Status *__restrict__ stt,
+                                                               double *__restrict__ out,
+                                                               int64_t count)
+{
+    if (stt->err[kErrIndex] == 0)
+        return;
+    const double nan = __builtin_nan("");
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < count;
+         e += (int64_t)gridDim.x * blockDim.x)
+        out[e] = nan;
+}
+
 // Start-up: the predicted accelerations become the first evaluation's a.
 __global__ __launch_bounds__(256) void k_copy_acc_to_jrec(Arrays A, int n, int split)
 {
@@ -580,6 +614,27 @@ hipError_t launch_get_predicted(const Arrays &A, int64_t n, double *xp, double *
 {
     hipLaunchKernelGGL(k_get_predicted, dim3(blocks_for(n, 256)), dim3(256), 0, st, A.jrec, (int)n,
                        xp, vp, ap);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack_records(const double *m, const double *xp, const double *vp,
+                               const double *ap, int64_t n, double *jrec, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_pack_records, dim3(blocks_for(n, 256)), dim3(256), 0, st, m, xp, vp, ap,
+                       (int)n, jrec);
+    return hipGetLastError();
+}
+
+hipError_t launch_poison_on_index_error(const Status *stt, double *out, int64_t count,
+                                        hipStream_t st)
+{
+    if (count <= 0)
+        return hipSuccess;
+    int64_t blocks = (count + 255) / 256;
+    if (blocks > 1024)
+        blocks = 1024;
+    hipLaunchKernelGGL(k_poison_on_index_error, dim3((unsigned)blocks), dim3(256), 0, st, stt, out,
+                       count);
     return hipGetLastError();
 }
 
