@@ -43,7 +43,7 @@ METRIC = "pairwise interactions/s (acc+jerk+snap) and % of FP64/FP32 vector peak
 PEAK_FP32_TFLOPS = 157.3           # the chip's FP32 vector peak (packed instructions)
 # sources of the evaluation kernel; the traffic figure below is valid only for them
 KERNEL_SRCS = [os.path.join(ROOT, "paper_1812_00367_amd", "csrc", f)
-               for f in ("nbody_kernels.hip", "nb_device.h", "nb_internal.h")]
+               for f in ("nbody_kernels.hip", "nbody_sym.hip", "nb_device.h", "nb_internal.h")]
 # HBM bytes per full-N FP64 evaluation launch from the FETCH_SIZE / WRITE_SIZE runs in
 # profiles/eval_fp64_plummer65536.md, keyed by the sha256 prefix of those sources (a
 # key is moved to a new hash only when the evaluation kernels' gfx950 assembly is
@@ -52,6 +52,15 @@ TRAFFIC = {"19f9c23fbeb8fc9a": {"fp64": 2.00 * 21978 * 1024 + 81920 * 1024}}
 # Flops per interaction the evaluation kernels execute (SQ_INSTS_VALU_FLOPS_FP64 /
 # _FP32 x 64 lanes / N^2, same profile), keyed the same way.
 EXECUTED_FLOPS = {"19f9c23fbeb8fc9a": {"fp64": 88.0, "split": 86.0}}
+
+
+def kernel_name(shape, fp64):
+    """The evaluation kernel a launch shape (nb_eval_config's report) selects."""
+    if not fp64:
+        return "k_eval_split"
+    if shape["ipl"] == 0:
+        return "k_eval_sym"   # every body active: each pair once, added to both bodies
+    return "k_eval_lanes_f64" if shape["ipl"] < 0 else "k_eval_f64"
 
 
 def kernel_sources_hash():
@@ -93,6 +102,9 @@ def parse():
     ap.add_argument("--energy-seconds", type=float, default=3.0,
                     help="length of the untimed run of the same step under the GPU energy "
                          "counter (0 = skip)")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the split-precision, ensemble and serving objects of the "
+                         "default line")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run one device-to-device copy of this many MiB (a known-size "
                          "kernel against which HBM byte counters are scaled)")
@@ -237,7 +249,7 @@ def main():
                    "eta": 0.45, "level": kmax, "eval_shape": shape},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak,
                      "unit": "TFLOP/s", "frac": achieved / peak, "traffic": traffic,
-                     "kernel": "k_eval_f64" if prec == nb.NB_FP64 else "k_eval_split",
+                     "kernel": kernel_name(shape, prec == nb.NB_FP64),
                      "flop_per_interaction": FLOP_PER_INTERACTION,
                      "algorithmic_bytes": 80 * n + 152 * n,
                      "eval_ms_avg": eval_avg_s * 1e3, "kernel_src": src_hash,
@@ -253,9 +265,68 @@ def main():
         result["crackle"] = crackle_leg(sim, n, stream)
     if args.energy_seconds > 0:
         result["energy_per_interaction"] = energy_leg(restore, one_step, n, args.energy_seconds)
+    if not args.no_extras and prec == nb.NB_FP64:
+        del sim
+        torch.cuda.empty_cache()
+        result["split"] = split_leg(ic, n)
+        result["ensemble"] = ensemble_workload(512, 0.25, 0, ("fp64",), 32)
+        result["serving"] = serving_workload([3.0], count=12, steps_per_call=32)
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(ic, n, args.cpu_seconds)
     print(json.dumps(result), flush=True)
+
+
+def split_leg(ic, n, reps=10):
+    """The full N x N evaluation of the sphere's initial state (predicted accelerations:
+    the smooth Plummer field) on the split-precision path and on the FP64 path, each
+    timed over `reps` calls: interactions/s, the ratio of the two, the stated rate as a
+    share of the FP64 and of the FP32 vector peak, and the split path's relative error
+    of a, j, s and phi against the FP64 path on every body (the FP64 path matches the
+    oracle within 1e-13, so this is the split path's error to that accuracy)."""
+    import numpy as np
+    import torch
+
+    import nbody_inputs as ni
+    import paper_1812_00367_amd as nb
+    dev = torch.device("cuda", 0)
+    ap = ni.plummer_mean_field_acc(ic.x)
+    idx = torch.arange(n, dtype=torch.int32, device=dev)
+    res, outs = {}, {}
+    for name, prec in (("fp64", nb.NB_FP64), ("split", nb.NB_SPLIT)):
+        sim = nb.Simulation(n, eps=EPS, dt_max_log2=DT_MAX, dt_min_log2=DT_MIN, precision=prec,
+                            device=dev)
+        sim.set_state(ic.m, ic.x, ic.v, a=ap)
+        sim.predict(0)
+        out = torch.empty((10, n), dtype=torch.float64, device=dev)
+        sim.evaluate_into(idx, out)
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(reps)]
+        for a, b in ev:
+            a.record(sim.stream)
+            sim.evaluate_into(idx, out)
+            b.record(sim.stream)
+        torch.cuda.synchronize()
+        ms = float(np.median([a.elapsed_time(b) for a, b in ev]))
+        res[name] = ms
+        outs[name] = out.cpu().numpy()
+        sim.close()
+        del sim
+    rate = n * n / (res["split"] / 1e3)
+    err = {}
+    for lab, c0, c1 in (("a", 0, 3), ("j", 3, 6), ("s", 6, 9), ("phi", 9, 10)):
+        ref = outs["fp64"][c0:c1]
+        e = np.linalg.norm(outs["split"][c0:c1] - ref, axis=0) / np.linalg.norm(ref, axis=0)
+        err[lab] = {"p50": float(np.median(e)), "p99": float(np.percentile(e, 99)),
+                    "max": float(e.max())}
+    return {"workload": f"plummer-{n} initial state, all {n} bodies active",
+            "median_ms": res["split"], "fp64_median_ms": res["fp64"],
+            "interactions_per_s": rate, "speedup_vs_fp64": res["fp64"] / res["split"],
+            "frac_fp64_peak": rate * FLOP_PER_INTERACTION / (PEAK_FP64_TFLOPS * 1e12),
+            "frac_fp32_peak": rate * FLOP_PER_INTERACTION / (PEAK_FP32_TFLOPS * 1e12),
+            "rel_error_vs_fp64_path": err,
+            "integrates": False,
+            "note": "evaluation only: the 6th-order step criterion cannot be driven by it "
+                    "(FP32 force noise amplified by the interpolated higher derivatives)"}
 
 
 FLOP_PER_INTERACTION_CRACKLE = 127   # the 79 above plus 48 for the crackle term
@@ -487,17 +558,24 @@ def ensemble_workload(count=512, t_end=0.25, jchunk=0, precisions=("fp64", "spli
                       f"{inter:.3e} interactions, {now - t0:.1f} s", file=sys.stderr, flush=True)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
-        e1 = np.array([sum(b.energy(j, tick_end)) for j in jobs])
-        de = np.abs((e1 - e0) / np.abs(e0))
+        # energy drift over the clusters that reached t_end: a cluster stopped by an
+        # error word would be extrapolated to t_end by the predictor, which is no
+        # energy error of the integration
+        done = [k for k, j in enumerate(jobs) if j not in errs]
+        e1 = np.array([sum(b.energy(jobs[k], tick_end)) for k in done])
+        de = np.abs((e1 - e0[done]) / np.abs(e0[done]))
         rate = inter / wall
         peak = PEAK_FP32_TFLOPS if name == "split" else PEAK_FP64_TFLOPS
-        res[name] = {"wall_s": wall, "startup_s": t_start, "batch_steps": steps, "steps_per_call": chunk,
+        res[name] = {"status": "completed" if not errs else
+                               f"not completed: {len(errs)} of {count} clusters stopped with an error word",
+                     "wall_s": wall, "startup_s": t_start, "batch_steps": steps, "steps_per_call": chunk,
                      "interactions": inter, "interactions_per_s": rate,
                      "tflops_at_79": rate * FLOP_PER_INTERACTION / 1e12,
                      "peak_frac": rate * FLOP_PER_INTERACTION / (peak * 1e12),
-                     "failed_clusters": len(errs),
-                     "energy_drift": {"p50": float(np.median(de)), "p99": float(np.percentile(de, 99)),
-                                      "max": float(de.max())}}
+                     "failed_clusters": len(errs), "completed_clusters": len(done),
+                     "energy_drift_completed": None if not done else
+                         {"p50": float(np.median(de)), "p99": float(np.percentile(de, 99)),
+                          "max": float(de.max())}}
         print(f"[c4 {name}] {steps} batch steps, {inter:.3e} interactions in {wall:.1f} s "
               f"= {rate:.3e}/s", file=sys.stderr, flush=True)
         b.close()

@@ -38,8 +38,13 @@
  * wait for the stream (they return values to the host). Input arrays passed to an
  * asynchronous call must stay valid until the stream reaches it.
  *
+ * Times: an int64 tick count rather than a double, so block times compare and
+ * divide exactly (a body's time is always a multiple of its power-of-two step).
+ *
  * Errors: no C++ exception crosses this boundary; every call returns an
- * nb_status and nb_last_error() gives a message. Argument errors found on the
+ * nb_status and nb_last_error() gives a message. NB_ERR_SPACE is the status for a
+ * workspace (or the fixed device array of nb_evaluate_static) too small for the
+ * request; the library never allocates, so it never runs out of memory itself. Argument errors found on the
  * host are returned at once. Errors found by kernels (an index out of range, a
  * non-finite corrector result, a step below dt_min) are latched in a device word
  * and returned by the next waiting call, which then clears the word.
@@ -87,8 +92,11 @@ typedef struct {
                              0 <= dt_max_log2 - dt_min_log2 <= 62 */
     int32_t precision;    /* nb_precision of nb_evaluate */
     int32_t flags;        /* 0 or NB_FLAG_START_CRACKLE */
-    int64_t partial_slots;/* capacity of the j-split partial-sum buffer in
-                             (split x active body) units; 0 = default max(4n, 2^20) */
+    int64_t partial_slots;/* capacity of the partial-sum buffer in units of 10 doubles
+                             (j-split x active body); 0 = default: max(4n, 2^20), raised
+                             for FP64 and 8192 <= n <= 131072 to the
+                             at most (512 + nb) 768 + nb (nb - 1) 384 slots, nb = ceil(n / 768),
+                             that the symmetric full evaluation needs (about n^2 / 1536) */
     void *stream;         /* hipStream_t for every launch; NULL = the null stream */
 } nb_params;
 
@@ -106,7 +114,8 @@ typedef struct {
     int32_t *level; /* the body's step level */
 } nb_state;
 
-/* Size in bytes of the device workspace a context with these parameters needs.
+/* Bookkeeping (no passage of the method): the device memory of a context.
+ * Size in bytes of the device workspace a context with these parameters needs.
  * Returns NB_ERR_ARG for invalid parameters. Touches no device. */
 nb_status nb_workspace_bytes(const nb_params *p, size_t *h_bytes);
 
@@ -122,7 +131,8 @@ void nb_destroy(nb_ctx *ctx);
 /* Message of the last error on this context ("" if none). Valid until the next call. */
 const char *nb_last_error(const nb_ctx *ctx);
 
-/* Load a state. m, x and v are required. a, j, s, c, a4n, a5n default to 0, tick to
+/* Bookkeeping (no passage of the method): state in and out of the workspace.
+ * Load a state. m, x and v are required. a, j, s, c, a4n, a5n default to 0, tick to
  * tick0 for every body and level to 0 when NULL. If tick is NULL the state is
  * "synchronised at tick0" and nb_start may be called; a full state (tick and
  * level given) resumes a run exactly (checkpoint restore). Asynchronous. */
@@ -137,20 +147,29 @@ nb_status nb_set_times(nb_ctx *ctx, const int64_t *d_tick, const int32_t *d_leve
 /* Copy the state into the non-NULL fields of dst (device arrays). Waits. */
 nb_status nb_get_state(nb_ctx *ctx, const nb_state *dst);
 
-/* Hermite start-up on a synchronised state: two evaluations of every body (the
+/* Passage: the start of the 6th-order Hermite scheme named in the paper's section
+ * "Code implementation" (the paper gives no start rule; this is the initial-step rule
+ * Delta0 = eta_init min(|a|/|j|, sqrt(|a|/|s|)) with power-of-two quantisation).
+ * Hermite start-up on a synchronised state: two evaluations of every body (the
  * first gives a and j, the second s with the predicted accelerations set to the
  * first a), c = 0, then the initial-step rule for every body. Asynchronous; a
  * non-finite result (e.g. two bodies at one place with eps = 0) is reported by the
  * next waiting call as NB_ERR_NUMERIC. */
 nb_status nb_start(nb_ctx *ctx);
 
-/* Block-step selection: tick_next = min over bodies of (tick + step) and the
+/* Passage: the block time steps of the paper's section "Code implementation"
+ * (individual power-of-two steps; Makino 1991). Split out of nb_timesteps so the
+ * active list is a device array that the other calls take as they are.
+ * Block-step selection: tick_next = min over bodies of (tick + step) and the
  * ascending list of bodies with tick + step == tick_next, written to d_idx_out
  * (capacity n). Returns the count in *h_n_act and the time in *h_tick_next. Waits. */
 nb_status nb_active(nb_ctx *ctx, int32_t *d_idx_out, int64_t *h_n_act,
                     int64_t *h_tick_next);
 
-/* Predict every body to tick (>= every body's own time) with its Taylor series
+/* Passage: the predictor of the 6th-order Hermite scheme (section "Code
+ * implementation"; Nitadori & Makino 2008): x, v, a extrapolated by their Taylor
+ * series up to the interpolated third derivative of a.
+ * Predict every body to tick (>= every body's own time) with its Taylor series
  * up to the third derivative of a; the result feeds nb_evaluate. Asynchronous. */
 nb_status nb_predict(nb_ctx *ctx, int64_t tick);
 
@@ -158,9 +177,18 @@ nb_status nb_predict(nb_ctx *ctx, int64_t tick);
  * nb_predict into [3][n] device arrays (NULL skipped). Asynchronous. */
 nb_status nb_get_predicted(nb_ctx *ctx, double *d_xp, double *d_vp, double *d_ap);
 
-/* Acceleration, jerk, snap and potential of the n_act bodies d_idx against all
+/* Passage: the O(N^2) force evaluation the paper's section "Performance results"
+ * measures, in double precision for distances and accelerations or in the
+ * extended-precision (float-float) variant of section "Code implementation"; the
+ * pairwise acceleration, jerk and snap of the 6th-order Hermite scheme (Nitadori &
+ * Makino 2008) with Plummer softening.
+ * Acceleration, jerk, snap and potential of the n_act bodies d_idx against all
  * n predicted bodies (self pair excluded), in the precision chosen at
- * nb_create. The result is kept for nb_correct and, if d_out is not NULL, also
+ * nb_create. In FP64, when every body is active (n_act = n >= 8192) and the
+ * partial-sum buffer holds its partial sums (the default capacity does up to
+ * n = 131072), each pair is computed once and added to both bodies (the terms are
+ * antisymmetric in the pair apart from the masses); otherwise each active body sums
+ * over all bodies. Both agree with the exact sums to FP64 rounding. The result is kept for nb_correct and, if d_out is not NULL, also
  * written to d_out[10][n_act]. n_act = 0 is a no-op. Asynchronous. */
 nb_status nb_evaluate(nb_ctx *ctx, const int32_t *d_idx, int64_t n_act, double *d_out);
 
@@ -192,9 +220,11 @@ nb_status nb_evaluate_crackle(nb_ctx *c, const int32_t *d_idx, int64_t n_act, do
  *   stream: hipStream_t, NULL = the null stream. Stream-ordered, returns without
  *   waiting; every kernel it enqueues is a plain kernel launch (no memset), so the
  *   call can be captured into a HIP graph.
- * It takes the evaluation kernels with the launch shapes of nb_evaluate (default
- * table and partial-sum capacity), so its result is bitwise that of nb_evaluate on
- * a context of n bodies.
+ * It takes the one-sided evaluation kernels with the launch shapes of nb_evaluate
+ * (default table and partial-sum capacity), so for n_act < n its result is bitwise
+ * that of nb_evaluate on a context of n bodies; for n_act = n nb_evaluate may take
+ * the pairwise-symmetric kernel instead, and the two agree to the FP64 rounding of
+ * the sums.
  * Errors: NB_ERR_ARG for n outside [1, 2^30], n_act outside [0, n], eps < 0 or a
  * NULL pointer; NB_ERR_SPACE (nothing enqueued) when the j-records (80 n bytes)
  * plus the partial sums of the launch shape (80 S n_act bytes) do not fit the array;
@@ -214,46 +244,65 @@ nb_status nb_evaluate_static(int64_t n, const double *d_m, const double *d_xp, c
 nb_status nb_set_evaluation(nb_ctx *ctx, const int32_t *d_idx, int64_t n_act,
                             const double *d_in);
 
-/* Launch shape of nb_evaluate, for tuning and tests: h_cfg = {bodies per lane
- * (1 or 2), waves per workgroup, LDS tile (bodies), j-splits S (>= 1)}, with
- * (waves, tile) one of (1, 64), (1, 128), (2, 128), (1, 256), (2, 256), (4, 256).
- * All zeros (or h_cfg NULL) returns to the launch table. The shape never changes results
- * beyond FP64 rounding of the split sums. Host-only; returns NB_ERR_ARG for an
+/* Launch shape of nb_evaluate, for tuning and tests: h_cfg = {ipl, waves per
+ * workgroup, tile, j-splits S (>= 1)}. Two kernel families:
+ *   - ipl = 1 or 2 active bodies per lane (each lane sweeps every record of its
+ *     j-split, read from LDS as wave-wide broadcasts), (waves, tile) one of (1, 64),
+ *     (1, 128), (2, 128), (1, 256), (2, 256), (4, 256) with tile the LDS tile in bodies;
+ *   - FP64 only, for small active sets: ipl = -Pmax, Pmax a power of two <= 64: a wave
+ *     holds P = min(Pmax, the power of two >= n_act) active bodies on 64 / P lanes
+ *     each (lane w of a body takes records w, w + 64/P, ... of the split, and the
+ *     lane sums are combined by a fixed butterfly); waves 1; tile 64 (LDS tiles of 64
+ *     records) or 0 (records read straight from memory).
+ * All zeros (or h_cfg NULL) returns to the launch table. The shape never changes
+ * results beyond FP64 rounding of the split sums. Host-only; returns NB_ERR_ARG for an
  * unsupported combination. h_shape_out (may be NULL) receives the shape the next
- * call with n_act bodies will use: {ipl, waves, tile, jchunk, splits, iblocks}. */
+ * call with n_act bodies will use: {ipl (for the small-set kernel: -P), waves, tile,
+ * jchunk, splits, iblocks}. */
 nb_status nb_eval_config(nb_ctx *ctx, const int32_t *h_cfg, int64_t n_act,
                          int32_t *h_shape_out);
 
 /* Launch-shape table of nb_evaluate, as produced by the tuner
- * (paper_1812_00367_amd/tune.py): nrows rows of five int32 {n_act_max, bodies per
- * lane, waves per workgroup, LDS tile, target waves}, n_act_max strictly
- * increasing. A call with n_act bodies uses the first row with n_act <= n_act_max
- * (the last row also covers larger sets); the target sets the j-split count
- * S ~ target / (waves along the active bodies). Supported shapes are those listed
- * for nb_eval_config. nrows = 0 restores the built-in table. A forced shape from
- * nb_eval_config takes precedence. Host-only. */
+ * (paper_1812_00367_amd/tune.py): nrows rows of five int32 {n_act_max, ipl, waves
+ * per workgroup, tile, target waves}, n_act_max strictly increasing. A call with
+ * n_act bodies uses the first row with n_act <= n_act_max (the last row also covers
+ * larger sets); the target sets the j-split count S ~ target / (waves along the
+ * active bodies). Supported shapes are those listed for nb_eval_config. nrows = 0
+ * restores the built-in table. A forced shape from nb_eval_config takes precedence.
+ * Host-only. */
 nb_status nb_eval_table(nb_ctx *ctx, const int32_t *h_rows, int32_t nrows);
 
-/* Hermite 6th-order corrector of the bodies of the last nb_evaluate (same d_idx,
+/* Passage: the corrector of the 6th-order Hermite scheme (section "Code
+ * implementation"; Nitadori & Makino 2008), with the third to fifth derivatives of a
+ * from the quintic through (a, j, s) at both ends of the step.
+ * Hermite 6th-order corrector of the bodies of the last nb_evaluate (same d_idx,
  * n_act) to tick, using that evaluation. Updates x, v, a, j, s, c, a4n, a5n and
  * sets their time to tick. Asynchronous. The kernel checks that d_idx is strictly
  * ascending (a body listed twice would be corrected twice): otherwise the next
  * waiting call returns NB_ERR_ARG and the listed bodies' state is undefined. */
 nb_status nb_correct(nb_ctx *ctx, const int32_t *d_idx, int64_t n_act, int64_t tick);
 
-/* New step levels of the bodies d_idx at their current time: the 6th-order
+/* Passage: the block time steps of section "Code implementation": the generalised
+ * Aarseth criterion of order 6, Delta = eta [(sqrt(|a||s|) + |j|) / (sqrt(|a3||a5|) +
+ * |a4|)]^(1/3) (Nitadori & Makino 2008), quantised to powers of two with the block
+ * rules of Makino 1991 and Aarseth 2003. The next active list is not returned here
+ * but by nb_active.
+ * New step levels of the bodies d_idx at their current time: the 6th-order
  * criterion and the block rules (init = 0), or the initial-step rule (init = 1).
  * Asynchronous; a body needing a step below dt_min is reported by the next
  * waiting call as NB_ERR_NUMERIC. */
 nb_status nb_timesteps(nb_ctx *ctx, const int32_t *d_idx, int64_t n_act, int init);
 
-/* One whole block step: nb_active, nb_predict, nb_evaluate, nb_correct and
+/* Passage: one cycle of the block-step scheme of section "Code implementation".
+ * One whole block step: nb_active, nb_predict, nb_evaluate, nb_correct and
  * nb_timesteps in order, with the active list kept in the workspace. Returns the
  * step's time and size. If tick_limit >= 0 and the next block time is beyond it,
  * nothing is done and *h_n_act is 0. Waits (after selecting the active set). */
 nb_status nb_step(nb_ctx *ctx, int64_t tick_limit, int64_t *h_n_act, int64_t *h_tick_next);
 
-/* Total energy at tick: every body is predicted to tick (this overwrites the
+/* Passage: the energy diagnostic of a direct N-body code (the paper reports no energy
+ * error; this is the softened total energy used to judge the integration).
+ * Total energy at tick: every body is predicted to tick (this overwrites the
  * predicted state), then E_kin = sum m v^2 / 2 and
  * E_pot = -1/2 sum_i sum_{j != i} m_i m_j / sqrt(r^2 + eps^2). Waits. */
 nb_status nb_energy(nb_ctx *ctx, int64_t tick, double *h_ekin, double *h_epot);

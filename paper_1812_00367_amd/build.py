@@ -17,7 +17,8 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libnbody.so")
-SOURCES = ["nbody_abi.hip", "nbody_kernels.hip", "nbody_batch.hip", "nbody_crackle.hip"]
+SOURCES = ["nbody_abi.hip", "nbody_kernels.hip", "nbody_batch.hip", "nbody_crackle.hip",
+           "nbody_sym.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 

@@ -256,6 +256,123 @@ __device__ __forceinline__ void tiles_f64(const double *__restrict__ jrec, int j
     }
 }
 
+// ------------------------------------------- W lanes per active body (FP64) ----
+// Small active sets: W lanes (a power of two) share one active body, lane w of a body
+// taking records w, w + W, ... of a j-range; the W partial sums of a body are then
+// combined by a fixed butterfly, so the result depends only on W and the range.
+constexpr int kLaneStageD = kLaneTile * 5 / 64;  // 16-byte chunks per lane per tile
+
+template <typename T>
+__device__ __forceinline__ T lane_butterfly(T v, int W)
+{
+    for (int o = W >> 1; o > 0; o >>= 1)
+        v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+struct Rec64 {
+    double2 p0, p1, p2, p3, p4;
+};
+
+__device__ __forceinline__ Rec64 load_rec64(const double2 *__restrict__ src, int j)
+{
+    const double2 *r = src + (size_t)j * 5;
+    return Rec64{r[0], r[1], r[2], r[3], r[4]};
+}
+
+// Rounds k = 0, 1, ...: lane w takes record jbeg + k W + w. Loads run two rounds
+// ahead. A record past jend is replaced by jbeg's and masked like the self pair (its
+// index set to the lane's own body); masking is used only on rounds that hold the
+// wave's own bodies or the end of the range.
+__device__ __forceinline__ void sweep_direct_f64(const double2 *__restrict__ src, int jbeg, int jend,
+                                                 int W, int w, I64 &b, int lo, int hi, double eps2)
+{
+    const I64(&one)[1] = reinterpret_cast<const I64(&)[1]>(b);
+    const int rounds = (jend - jbeg + W - 1) / W;
+    auto idx = [&](int k) { return jbeg + k * W + w; };
+    auto at = [&](int k) { const int j = idx(k); return j < jend ? j : jbeg; };
+    Rec64 c = load_rec64(src, at(0));
+    Rec64 nx = load_rec64(src, at(rounds > 1 ? 1 : 0));
+    for (int k = 0; k < rounds; ++k) {
+        const Rec64 f = load_rec64(src, at(k + 2 < rounds ? k + 2 : k));
+        const int r0 = jbeg + k * W;
+        if (r0 + W <= jend && ((hi < r0 || lo >= r0 + W) || !wave_has_self(one, r0, W))) {
+            interact_f64<false>(b, c.p0, c.p1, c.p2, c.p3, c.p4, eps2, 0);
+        } else {
+            const int j = idx(k);
+            interact_f64<true>(b, c.p0, c.p1, c.p2, c.p3, c.p4, eps2, j < jend ? j : b.self);
+        }
+        c = nx;
+        nx = f;
+    }
+}
+
+// LDS tiles of 64 records, double-buffered through registers (as the single-system
+// kernel): lane w reads records w, w + W, ... of each tile.
+__device__ __forceinline__ void sweep_lds_f64(const double2 *__restrict__ src, int jbeg, int jend,
+                                              int W, int lw, int w, I64 &b, int lo, int hi, double eps2,
+                                              double2 (*lds)[kLaneTile * 5])
+{
+    const int lane = threadIdx.x;
+    const int ntiles = (jend - jbeg + kLaneTile - 1) / kLaneTile;
+    double2 stage[kLaneStageD];
+    int valid = 0;
+    auto gload = [&](int t) {
+        const int j0 = jbeg + t * kLaneTile;
+        valid = (jend - j0) * 5;
+#pragma unroll
+        for (int c = 0; c < kLaneStageD; ++c) {
+            const int ch = c * 64 + lane;
+            stage[c] = src[ch < valid ? (size_t)j0 * 5 + ch : 0];
+        }
+    };
+    auto lstore = [&](int buf) {
+#pragma unroll
+        for (int c = 0; c < kLaneStageD; ++c) {
+            const int ch = c * 64 + lane;
+            const bool ok = ch < valid;
+            const int part5 = ch % 5;
+            double2 v;
+            v.x = ok ? stage[c].x : (part5 <= 1 ? kFar : 0.0);
+            v.y = ok ? stage[c].y : (part5 == 0 ? kFar : 0.0);
+            lds[buf][ch] = v;
+        }
+    };
+    if (ntiles > 0) {
+        gload(0);
+        lstore(0);
+    }
+    __syncthreads();
+    const int per = kLaneTile >> lw;  // records per lane per tile
+    for (int t = 0; t < ntiles; ++t) {
+        const int buf = t & 1;
+        if (t + 1 < ntiles)
+            gload(t + 1);
+        const int j0 = jbeg + t * kLaneTile;
+        const double2 *L = lds[buf] + w * 5;
+        const int step = W * 5;
+        if (hi < j0 || lo >= j0 + kLaneTile) {
+            double2 p0 = L[0], p1 = L[1], p2 = L[2], p3 = L[3], p4 = L[4];
+            for (int k = 0; k < per; ++k) {
+                const int nx = (k + 1 < per ? k + 1 : k) * step;
+                const double2 n0 = L[nx + 0], n1 = L[nx + 1], n2 = L[nx + 2], n3 = L[nx + 3],
+                              n4 = L[nx + 4];
+                interact_f64<false>(b, p0, p1, p2, p3, p4, eps2, 0);
+                p0 = n0; p1 = n1; p2 = n2; p3 = n3; p4 = n4;
+            }
+        } else {
+            for (int k = 0; k < per; ++k) {
+                const int e = k * step;
+                interact_f64<true>(b, L[e + 0], L[e + 1], L[e + 2], L[e + 3], L[e + 4], eps2,
+                                   j0 + w + k * W);
+            }
+        }
+        if (t + 1 < ntiles)
+            lstore(buf ^ 1);
+        __syncthreads();
+    }
+}
+
 // ------------------------------------------------------ pairwise (split) ----
 // Same quantities with the paper's extended-precision idea applied the other way
 // round: the coordinate difference is taken in float-float,

@@ -50,13 +50,17 @@ struct Arrays {
 
 // Launch shape of one evaluation.
 struct EvalPlan {
-    int ipl;     // active bodies per lane
+    int ipl;     // active bodies per lane (1, 2); for the small-set kernel, minus the
+                 // active bodies per wave
     int waves;   // waves per workgroup
-    int tile;    // j-records per LDS tile
-    int jchunk;  // j-records per split (multiple of tile)
+    int tile;    // j-records per LDS tile (0: the small-set kernel reads memory directly)
+    int jchunk;  // j-records per split (multiple of the tile, or of 64)
     int splits;  // number of j-splits S
     int iblocks; // workgroups along the active bodies
+    int lw;      // small-set kernel: log2 of the lanes per active body; -1 otherwise
 };
+
+constexpr int kLaneTile = 64;  // records per LDS tile of the W-lanes-per-body sweeps
 
 constexpr int kActBS = 256;
 constexpr int kActPerThread = 8;
@@ -90,9 +94,12 @@ struct EvalRow {
 };
 constexpr int kMaxEvalRows = 32;
 
-// Shapes with a compiled kernel: ipl in {1, 2}; (waves, tile) in {(1, 64), (1, 128),
-// (2, 128), (1, 256), (2, 256), (4, 256)} (a tile's 16-byte chunks split evenly).
-bool eval_shape_supported(int ipl, int waves, int tile);
+// Shapes with a compiled kernel: ipl in {1, 2} with (waves, tile) in {(1, 64),
+// (1, 128), (2, 128), (1, 256), (2, 256), (4, 256)} (a tile's 16-byte chunks split
+// evenly); or, FP64 only, the small-set kernel: ipl = -Pmax (Pmax in {1, 2, 4, ..., 64}:
+// at most Pmax active bodies per wave, each on 64 / P lanes with P = min(Pmax, the
+// power of two >= n_act)), waves 1, tile 64 (LDS) or 0 (direct from memory).
+bool eval_shape_supported(int ipl, int waves, int tile, bool split);
 // Shape from a table (nrows == 0: the built-in table for the precision).
 EvalPlan plan_eval(int64_t n, int64_t n_act, int64_t partial_slots, bool split,
                    const EvalRow *rows, int nrows);
@@ -100,6 +107,22 @@ EvalPlan plan_eval(int64_t n, int64_t n_act, int64_t partial_slots, bool split,
 EvalPlan plan_eval_fixed(int64_t n, int64_t n_act, int ipl, int waves, int tile, int64_t S);
 hipError_t launch_eval(const Arrays &A, const EvalPlan &P, int64_t n, const int32_t *idx,
                        int64_t n_act, double eps, bool split, double *out, hipStream_t st);
+
+// Evaluation of every body against every body with each pair computed once
+// (nbody_sym.hip): blocks of B bodies, a persistent grid of G workgroups over the
+// units (row block, half block), partial sums in a row buffer and a column buffer
+// (row_slots + col_slots doubles), then a fixed-order reduction into the index order.
+// The geometry (and so the summation order) depends on n and G only.
+constexpr int kSymWaves = 4;
+constexpr int kSymGroups = 512;  // workgroups (fixed, so the summation order is too)
+struct SymPlan {
+    int B, nb, G, parts;  // block size, blocks, workgroups, parts per block
+    int64_t units, row_slots, col_slots;
+};
+SymPlan plan_sym(int64_t n, int G);
+hipError_t launch_eval_sym(const Arrays &A, const SymPlan &P, int64_t n, const int32_t *idx,
+                           int64_t n_act, double eps, double *rowbuf, double *colbuf,
+                           double *dst, double *dst2, hipStream_t st);
 
 hipError_t launch_correct(const Arrays &A, int64_t n, const int32_t *idx, int64_t n_act,
                           int64_t tick, int dt_min_log2, hipStream_t st);

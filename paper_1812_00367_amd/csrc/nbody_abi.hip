@@ -42,12 +42,29 @@ constexpr int64_t kMaxN = (int64_t)1 << 30;
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+// Full evaluations (every body active) of systems of at least kSymMinN bodies take
+// the pairwise-symmetric kernel when its partial sums fit the partial buffer; the
+// default buffer holds them up to kSymDefaultMaxN bodies.
+constexpr int64_t kSymMinN = 8192;
+constexpr int64_t kSymDefaultMaxN = 131072;
+
+int64_t sym_slots(int64_t n)
+{
+    const nb::SymPlan S = nb::plan_sym(n, nb::kSymGroups);
+    return (S.row_slots + S.col_slots + 9) / 10;
+}
+
 int64_t partial_slots_of(const nb_params *p)
 {
     if (p->partial_slots > 0)
         return p->partial_slots;
     const int64_t a = 4 * p->n, b = (int64_t)1 << 20;
-    return a > b ? a : b;
+    int64_t s = a > b ? a : b;
+    if (p->precision == NB_FP64 && p->n >= kSymMinN && p->n <= kSymDefaultMaxN) {
+        const int64_t need = sym_slots(p->n);
+        s = need > s ? need : s;
+    }
+    return s;
 }
 
 // Carve the workspace (base may be null to only measure). Returns the total size.
@@ -171,6 +188,15 @@ nb_status do_predict(nb_ctx *c, int64_t tick)
     return NB_OK;
 }
 
+// Whether an evaluation of n_act bodies takes the pairwise-symmetric kernel: FP64,
+// every body active, no forced launch shape, and room for its partial sums.
+bool use_sym(const nb_ctx *c, int64_t n_act)
+{
+    if (c->p.precision != NB_FP64 || c->cfg[0] || n_act != c->p.n || c->p.n < kSymMinN)
+        return false;
+    return sym_slots(c->p.n) <= partial_slots_of(&c->p);
+}
+
 nb::EvalPlan make_plan(const nb_ctx *c, int64_t n_act)
 {
     if (c->cfg[0])
@@ -181,7 +207,12 @@ nb::EvalPlan make_plan(const nb_ctx *c, int64_t n_act)
 
 nb_status do_evaluate(nb_ctx *c, const int32_t *idx, int64_t n_act, double *out)
 {
-    if (n_act > 0) {
+    if (n_act > 0 && use_sym(c, n_act)) {
+        const nb::SymPlan S = nb::plan_sym(c->p.n, nb::kSymGroups);
+        double *rowbuf = c->A.part, *colbuf = c->A.part + S.row_slots;
+        NB_HIP(c, nb::launch_eval_sym(c->A, S, c->p.n, idx, n_act, c->p.eps, rowbuf, colbuf,
+                                      c->A.evalbuf, out, c->st));
+    } else if (n_act > 0) {
         const nb::EvalPlan P = make_plan(c, n_act);
         if (P.splits > 1 && (int64_t)P.splits * n_act > partial_slots_of(&c->p))
             return fail(c, NB_ERR_SPACE, "partial-sum buffer too small");
@@ -204,6 +235,9 @@ namespace nb {
 // checked by interleaved timings of the candidates at 1024, 8192 and 65536 active
 // bodies.
 static const EvalRow kDefaultF64[] = {
+    {1, -1, 1, 0, 256},
+    {8, -8, 1, 0, 1024},
+    {64, -16, 1, 64, 2048},
     {128, 1, 1, 64, 1024},
     {512, 1, 2, 128, 2048},
     {2048, 2, 4, 256, 2048},
@@ -216,29 +250,54 @@ static const EvalRow kDefaultSplit[] = {
     {1 << 30, 1, 4, 256, 16384},
 };
 
-bool eval_shape_supported(int ipl, int waves, int tile)
+bool eval_shape_supported(int ipl, int waves, int tile, bool split)
 {
+    if (ipl < 0) {
+        const int pmax = -ipl;
+        return !split && pmax <= 64 && (pmax & (pmax - 1)) == 0 && waves == 1 &&
+               (tile == 64 || tile == 0);
+    }
     if (ipl != 1 && ipl != 2)
         return false;
     return (waves == 1 && (tile == 64 || tile == 128 || tile == 256)) ||
            (waves == 2 && (tile == 128 || tile == 256)) || (waves == 4 && tile == 256);
 }
 
+// The j-split of n bodies into about S ranges of whole `unit`-record blocks.
+static void split_range(int64_t n, int64_t S, int unit, EvalPlan &P)
+{
+    const int64_t max_units = (n + unit - 1) / unit;
+    if (S > max_units) S = max_units;
+    if (S < 1) S = 1;
+    int64_t per = (n + S - 1) / S;
+    per = (per + unit - 1) / unit * unit;
+    P.jchunk = (int)per;
+    P.splits = (int)((n + per - 1) / per);
+}
+
 EvalPlan plan_eval_fixed(int64_t n, int64_t n_act, int ipl, int waves, int tile, int64_t S)
 {
     EvalPlan P{};
-    P.ipl = ipl;
     P.waves = waves;
     P.tile = tile;
+    if (ipl < 0) {
+        // small-set kernel: P active bodies per wave, 64 / P lanes each
+        int pw = 1;
+        while (pw < n_act && pw < -ipl)
+            pw <<= 1;
+        P.ipl = -pw;
+        P.lw = 0;
+        while ((64 >> P.lw) > pw)
+            ++P.lw;
+        P.iblocks = (int)((n_act + pw - 1) / pw);
+        split_range(n, S, kLaneTile, P);
+        return P;
+    }
+    P.ipl = ipl;
+    P.lw = -1;
     const int64_t per_block = (int64_t)ipl * 64 * waves;
     P.iblocks = (int)((n_act + per_block - 1) / per_block);
-    const int64_t max_tiles = (n + tile - 1) / tile;
-    if (S > max_tiles) S = max_tiles;
-    if (S < 1) S = 1;
-    int64_t per = (n + S - 1) / S;
-    per = (per + tile - 1) / tile * tile;
-    P.jchunk = (int)per;
-    P.splits = (int)((n + per - 1) / per);
+    split_range(n, S, tile, P);
     return P;
 }
 
@@ -255,8 +314,17 @@ EvalPlan plan_eval(int64_t n, int64_t n_act, int64_t partial_slots, bool split,
             r = &rows[k];
             break;
         }
-    const int64_t per_block = (int64_t)r->ipl * 64 * r->waves;
-    const int64_t waves_i = (n_act + per_block - 1) / per_block * r->waves;
+    // waves along the active bodies, then S ~ target / that
+    int64_t waves_i;
+    if (r->ipl < 0) {
+        int64_t pw = 1;
+        while (pw < n_act && pw < -r->ipl)
+            pw <<= 1;
+        waves_i = (n_act + pw - 1) / pw;
+    } else {
+        const int64_t per_block = (int64_t)r->ipl * 64 * r->waves;
+        waves_i = (n_act + per_block - 1) / per_block * r->waves;
+    }
     int64_t S = (r->target_waves + waves_i - 1) / waves_i;
     const int64_t cap = partial_slots / (n_act > 0 ? n_act : 1);
     if (S > cap) S = cap;
@@ -546,7 +614,8 @@ nb_status nb_evaluate_static(int64_t n, const double *d_m, const double *d_xp, c
     if (!d_m || !d_xp || !d_vp || !d_ap || !d_idx || !d_out)
         return NB_ERR_ARG;
     // the launch shape nb_evaluate uses for a context of n bodies with the default
-    // partial-sum capacity and the built-in table, so both give the same bits
+    // partial-sum capacity and the built-in table (the one-sided kernels only), so
+    // both give the same bits whenever nb_evaluate takes those kernels
     nb_params dp{};
     dp.n = n;
     dp.precision = NB_FP64;
@@ -604,7 +673,8 @@ nb_status nb_eval_config(nb_ctx *c, const int32_t *h_cfg, int64_t n_act, int32_t
         memcpy(cfg, h_cfg, sizeof cfg);
     const bool zero = !cfg[0] && !cfg[1] && !cfg[2] && !cfg[3];
     if (!zero) {
-        const bool ok = cfg[3] >= 1 && nb::eval_shape_supported(cfg[0], cfg[1], cfg[2]);
+        const bool ok = cfg[3] >= 1 &&
+                        nb::eval_shape_supported(cfg[0], cfg[1], cfg[2], c->p.precision == NB_SPLIT);
         if (!ok)
             return fail(c, NB_ERR_ARG, "unsupported launch shape {%d,%d,%d,%d}", cfg[0], cfg[1],
                         cfg[2], cfg[3]);
@@ -613,6 +683,16 @@ nb_status nb_eval_config(nb_ctx *c, const int32_t *h_cfg, int64_t n_act, int32_t
     if (h_shape_out) {
         if (n_act < 1 || n_act > c->p.n)
             return fail(c, NB_ERR_ARG, "n_act outside [1, n]");
+        if (use_sym(c, n_act)) {
+            const nb::SymPlan S = nb::plan_sym(c->p.n, nb::kSymGroups);
+            h_shape_out[0] = 0;
+            h_shape_out[1] = nb::kSymWaves;
+            h_shape_out[2] = 64;
+            h_shape_out[3] = S.B / S.parts;
+            h_shape_out[4] = (int32_t)S.units;
+            h_shape_out[5] = S.G;
+            return NB_OK;
+        }
         const nb::EvalPlan P = make_plan(c, n_act);
         h_shape_out[0] = P.ipl;
         h_shape_out[1] = P.waves;
@@ -632,7 +712,7 @@ nb_status nb_eval_table(nb_ctx *c, const int32_t *h_rows, int32_t nrows)
     for (int k = 0; k < nrows; ++k) {
         const int32_t *r = h_rows + 5 * k;
         if (r[0] < 1 || (k > 0 && r[0] <= h_rows[5 * (k - 1)]) || r[4] < 1 ||
-            !nb::eval_shape_supported(r[1], r[2], r[3]))
+            !nb::eval_shape_supported(r[1], r[2], r[3], c->p.precision == NB_SPLIT))
             return fail(c, NB_ERR_ARG, "bad table row %d {%d,%d,%d,%d,%d}", k, r[0], r[1], r[2],
                         r[3], r[4]);
     }

@@ -243,6 +243,58 @@ __global__ __launch_bounds__(64 * NW) void k_eval_split(Arrays A, int n, const i
     }
 }
 
+// --------------------------------------------- small active sets (FP64) ----
+// A one-wave workgroup holds P = 64 / W active bodies with W lanes each: lane w of a
+// body takes records w, w + W, ... of the workgroup's j-range, staged through LDS
+// tiles of 64 records or, for DIRECT, read straight from memory (a few records per
+// lane, where a tile would not hide the load latency). The W lane sums of a body are
+// combined by a fixed butterfly and written as the split's partial sums, so a wave
+// stays full for the one to a few dozen active bodies of a sparse block step.
+template <bool DIRECT>
+__global__ __launch_bounds__(64) void k_eval_lanes_f64(Arrays A, int n, const int32_t *__restrict__ idx,
+                                                       int n_act, double eps2, int lw, int jchunk,
+                                                       double *__restrict__ part, int nsplit)
+{
+    __shared__ double2 lds[DIRECT ? 1 : 2][kLaneTile * 5];
+    int g, split;
+    eval_block_coords(nsplit, g, split);
+    const int W = 1 << lw, w = (int)threadIdx.x & (W - 1);
+    const int slot = (g << (6 - lw)) + ((int)threadIdx.x >> lw);
+    int i = idx[slot < n_act ? slot : n_act - 1];
+    if ((unsigned)i >= (unsigned)n) {
+        raise_err(A.status, kErrIndex);
+        i = 0;
+    }
+    const double2 *__restrict__ src = reinterpret_cast<const double2 *>(A.jrec);
+    I64 b;
+    {
+        const double2 *r = src + (size_t)i * 5;
+        const double2 r0 = r[0], r1 = r[1], r2 = r[2], r3 = r[3], r4 = r[4];
+        b.x[0] = r0.x; b.x[1] = r0.y; b.x[2] = r1.x;
+        b.v[0] = r1.y; b.v[1] = r2.x; b.v[2] = r2.y;
+        b.a[0] = r3.x; b.a[1] = r3.y; b.a[2] = r4.x;
+#pragma unroll
+        for (int c = 0; c < 10; ++c)
+            b.acc[c] = 0.0;
+        b.self = i;
+    }
+    const int lo = wave_min_i32(i), hi = wave_max_i32(i);
+    const int jbeg = split * jchunk;
+    const int jend = min(n, jbeg + jchunk);
+    if constexpr (DIRECT)
+        sweep_direct_f64(src, jbeg, jend, W, w, b, lo, hi, eps2);
+    else
+        sweep_lds_f64(src, jbeg, jend, W, lw, w, b, lo, hi, eps2, lds);
+#pragma unroll
+    for (int c = 0; c < 10; ++c)
+        b.acc[c] = lane_butterfly(b.acc[c], W);
+    if (w == 0 && slot < n_act) {
+#pragma unroll
+        for (int c = 0; c < 10; ++c)
+            part[((size_t)split * 10 + c) * n_act + slot] = b.acc[c];
+    }
+}
+
 // Sum over the S j-splits, out[e] = sum_s part[s][e], in a fixed order: G threads
 // share an element, thread g adds s = g, g + G, ... in turn (four independent
 // chains, combined in a fixed pattern), then the G results are combined by a fixed
@@ -678,7 +730,19 @@ hipError_t launch_eval(const Arrays &A, const EvalPlan &P, int64_t n, const int3
 #define NB_SHAPE(I, W, T)                                                                  \
     else if (P.ipl == I && P.waves == W && P.tile == T) e =                                \
         run_eval<I, W, T>(A, P, n, idx, n_act, eps, split, dst, st);
-    if (false) e = hipErrorInvalidValue;
+    if (P.lw >= 0) {
+        if (split)
+            return hipErrorInvalidValue;
+        const bool xcd = P.splits > 1 && (P.splits % 8) == 0;
+        const dim3 grid = xcd ? dim3(P.iblocks * P.splits, 1) : dim3(P.iblocks, P.splits);
+        if (P.tile == 0)
+            hipLaunchKernelGGL(k_eval_lanes_f64<true>, grid, dim3(64), 0, st, A, (int)n, idx,
+                               (int)n_act, eps * eps, P.lw, P.jchunk, dst, P.splits);
+        else
+            hipLaunchKernelGGL(k_eval_lanes_f64<false>, grid, dim3(64), 0, st, A, (int)n, idx,
+                               (int)n_act, eps * eps, P.lw, P.jchunk, dst, P.splits);
+        e = hipGetLastError();
+    }
     NB_SHAPE(1, 1, 64) NB_SHAPE(1, 1, 128) NB_SHAPE(1, 2, 128) NB_SHAPE(1, 1, 256)
     NB_SHAPE(1, 2, 256) NB_SHAPE(1, 4, 256) NB_SHAPE(2, 1, 64) NB_SHAPE(2, 1, 128)
     NB_SHAPE(2, 2, 128) NB_SHAPE(2, 1, 256) NB_SHAPE(2, 2, 256) NB_SHAPE(2, 4, 256)

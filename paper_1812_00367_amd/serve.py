@@ -36,6 +36,8 @@ class Request:
     finished: float | None = None
     error: int = 0
     result: dict | None = field(default=None, repr=False)
+    # (tick_next, n_act) of every block step the job took, when the server traces
+    trace: list | None = field(default=None, repr=False)
 
     @property
     def n(self):
@@ -76,13 +78,18 @@ class Server:
 
     steps_per_call: batch steps enqueued between two scheduling decisions (one host
     wait each). keep_state: copy each finished job's final state to the host.
+    trace: record every job's block steps, (tick_next, n_act) each, in its request
+    (needs steps_per_call = 1, since a multi-step call reports only its last step).
     clock / sleep: time source (seconds) and wait, replaceable for tests."""
 
     def __init__(self, executor, steps_per_call=8, keep_state=False, clock=time.perf_counter,
-                 sleep=time.sleep):
+                 sleep=time.sleep, trace=False):
         self.ex = executor
         self.steps_per_call = int(steps_per_call)
+        if trace and self.steps_per_call != 1:
+            raise ValueError("tracing every block step needs steps_per_call = 1")
         self.keep_state = keep_state
+        self.trace = bool(trace)
         self.clock = clock
         self.sleep = sleep
 
@@ -110,6 +117,8 @@ class Server:
                     break
                 waiting.popleft()
                 r.admitted = self.clock() - t0
+                if self.trace:
+                    r.trace = []
                 resident[job] = r
             if not resident:
                 if waiting:
@@ -120,11 +129,15 @@ class Server:
                 continue
             peak_resident = max(peak_resident, len(resident))
             c0 = self.clock()
-            nact, _, err, it, _ = ex.run_steps(self.steps_per_call)
+            nact, tnext, err, it, _ = ex.run_steps(self.steps_per_call)
             t = self.clock() - t0
             busy += self.clock() - c0
             calls += 1
             inter += it
+            if self.trace:
+                for job, r in resident.items():
+                    if nact[job] > 0:
+                        r.trace.append((tnext[job], nact[job]))
             for job in list(resident):
                 if nact[job] == 0 or err[job]:
                     r = resident.pop(job)
@@ -137,12 +150,18 @@ class Server:
                         log(f"request {r.rid} ({r.kind}, n={r.n}) done at {t:.3f} s, "
                             f"latency {r.latency:.3f} s, error {r.error}")
         makespan = self.clock() - t0
-        lat = [r.latency for r in requests]
+        # latency percentiles over the requests that completed without an error (a
+        # failed job's latency is its time to failure); failures are counted apart
+        ok = [r for r in requests if not r.error]
+        lat = [r.latency for r in ok]
         wait = [r.admitted - r.arrival for r in requests]
         return {
             "requests": len(requests),
-            "failed": sum(1 for r in requests if r.error),
+            "completed": len(ok),
+            "failed": len(requests) - len(ok),
             "latency_p50_s": _percentile(lat, 50),
+            # with fewer than 100 completed requests p99 is interpolated between the
+            # two largest latencies; the maximum is reported beside it
             "latency_p99_s": _percentile(lat, 99),
             "latency_max_s": max(lat) if lat else None,
             "queue_wait_p50_s": _percentile(wait, 50),

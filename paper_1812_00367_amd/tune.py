@@ -26,8 +26,15 @@ import math
 
 SHAPES = [(1, 1, 64), (1, 1, 128), (1, 2, 128), (1, 1, 256), (1, 2, 256), (1, 4, 256),
           (2, 1, 64), (2, 1, 128), (2, 2, 128), (2, 1, 256), (2, 2, 256), (2, 4, 256)]
-TARGETS = [1024, 2048, 4096, 8192, 16384, 32768]
-DEFAULT_SIZES = [1, 4, 16, 64, 256, 1024, 4096, 16384, 65536]
+# the small-set kernel (FP64): at most P active bodies per wave on 64 / P lanes each,
+# records from LDS tiles (tile 64) or straight from memory (tile 0); timed only for
+# active sets up to SMALL_MAX
+SMALL_SHAPES = [(-p, 1, t) for t in (0, 64) for p in (1, 2, 4, 8, 16, 32, 64)]
+SMALL_MAX = 1024
+TARGETS = [128, 256, 512, 1024, 2048, 4096, 8192, 16384, 32768]
+# active-set sizes up to n / 2: a full set (n_act = n) takes the pairwise-symmetric
+# kernel, which the table does not choose
+DEFAULT_SIZES = [1, 2, 4, 8, 16, 32, 64, 128, 256, 1024, 4096, 16384, 32768]
 
 
 def time_eval(sim, idx, out, reps, warm):
@@ -46,13 +53,14 @@ def time_eval(sim, idx, out, reps, warm):
     return ms[len(ms) // 2]
 
 
-def tune(sim, sizes=None, seed=20, shapes=SHAPES, targets=TARGETS, log=None):
-    """Returns (rows, results); results[n_act] = (best_ms, shape, target, plan)."""
+def tune(sim, sizes=None, seed=20, shapes=SHAPES, targets=TARGETS, log=None, small=True):
+    """Returns (rows, results); results[n_act] = (best_ms, shape, target, plan).
+    small: also time the small-set kernel's shapes (FP64 contexts only)."""
     import torch
 
     import nbody_inputs as ni
     n = sim.n
-    sizes = [s for s in (sizes or DEFAULT_SIZES) if s <= n]
+    sizes = [s for s in (sizes or DEFAULT_SIZES) if s < n]
     out = torch.empty((10, n), dtype=torch.float64, device=sim.device)
     results = {}
     for k, na in enumerate(sizes):
@@ -61,7 +69,8 @@ def tune(sim, sizes=None, seed=20, shapes=SHAPES, targets=TARGETS, log=None):
         reps = 3 if work > 1e9 else 7
         best = None
         seen = set()
-        for shape in shapes:
+        cands = list(shapes) + (SMALL_SHAPES if small and na <= SMALL_MAX else [])
+        for shape in cands:
             for tw in targets:
                 sim.eval_table([(1 << 30, *shape, tw)])
                 plan = sim.eval_config(None, na)
@@ -148,6 +157,8 @@ def main():
     ap.add_argument("--n", type=int, default=65536)
     ap.add_argument("--precision", choices=("fp64", "split"), default="fp64")
     ap.add_argument("--seed", type=int, default=2)
+    ap.add_argument("--sizes", default="", help="comma-separated active-set sizes to tune "
+                    "(default: powers of two up to n / 2)")
     ap.add_argument("--batch", type=int, default=0,
                     help="tune the batch path instead, on an ensemble of this many Plummer "
                          "clusters (N log-uniform in [256, 16384], Kroupa masses) to t = 0.125")
@@ -177,7 +188,9 @@ def main():
                         precision=nb.NB_SPLIT if args.precision == "split" else nb.NB_FP64)
     sim.set_state(ic.m, ic.x, ic.v, a=ni.plummer_mean_field_acc(ic.x))
     sim.predict(0)
-    rows, results = tune(sim, log=lambda s: print(s, flush=True))
+    sizes = [int(v) for v in args.sizes.split(",")] if args.sizes else None
+    rows, results = tune(sim, sizes=sizes, log=lambda s: print(s, flush=True),
+                         small=args.precision == "fp64")
     print(json.dumps({"n": args.n, "precision": args.precision, "rows": rows,
                       "best_ms": {str(k): v[0] for k, v in results.items()}}), flush=True)
     print("C: " + ", ".join("{%d, %d, %d, %d, %d}" % tuple(r) for r in rows), flush=True)

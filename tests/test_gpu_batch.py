@@ -66,6 +66,37 @@ def states(b, jobs):
 
 
 # --------------------------------------------------------------- oracle parity --
+def test_batch_large_job_matches_oracle(nb):
+    """A 9000-body job (above 8192 bodies: after its first step the next block time
+    comes from the previous step's minima instead of a scan) beside two small ones,
+    run to its end with steps capped at 2^-6: the same block times, active counts
+    and final levels as the oracle's integration, positions and velocities within
+    1e-9."""
+    dt_max = -6
+    t_end = 1 << (dt_max - DT_MIN)
+    ics = [cluster(9000, 1200), cluster(300, 1201), cluster(2500, 1202)]
+    b = nb.Batch(12000, 3, eps=1e-4, dt_max_log2=dt_max, dt_min_log2=DT_MIN)
+    jobs = [b.add(ic.m, ic.x, ic.v, t_end) for ic in ics]
+    steps, inter, logs = run_to_end(b)
+    st = states(b, jobs)
+    for j, ic in zip(jobs, ics):
+        ost = oracle.State(m=ic.m, x=ic.x, v=ic.v)
+        osteps, ostt, osna, _ = oracle.integrate(ost, 1e-4, 0.45, 0.01, dt_max, DT_MIN, t_end)
+        gt = np.array([t for t, _ in logs[j]])
+        gn = np.array([k for _, k in logs[j]])
+        dx = np.abs(st[j]["x"] - ost.x).max()
+        dv = np.abs(st[j]["v"] - ost.v).max()
+        say("large-job batch: job", j, "n", ic.m.size, "steps gpu/oracle", len(gt), osteps,
+            "max |dx|", dx, "max |dv|", dv)
+        assert len(gt) == osteps
+        assert np.array_equal(gt, ostt) and np.array_equal(gn, osna)
+        assert np.all(st[j]["tick"] == t_end)
+        assert np.array_equal(st[j]["level"], ost.level)
+        assert dx < 1e-9 and dv < 1e-9, (j, dx, dv)
+    b.close()
+
+
+
 # default chunk factors of the item classes, and another setting of all three
 @pytest.mark.parametrize("factors", [None, (1, 8, 2)])
 def test_batch_jobs_match_oracle(nb, factors):
@@ -111,32 +142,39 @@ def test_batch_jobs_match_oracle(nb, factors):
 # ------------------------------------------------------- alone vs mix, bitwise --
 @pytest.mark.parametrize("precision", ["fp64", "split"])
 def test_batch_alone_and_mixed_are_bitwise_equal(nb, precision):
+    """Two target jobs, 777 and 9000 bodies (the larger one above 8192, so after its
+    first step its next block time comes from the previous step's minima instead of
+    a scan), each run alone and then in a mix where they sit at other pool offsets,
+    another job ends earlier, one is removed mid-run and two are admitted later: every
+    field of both targets' final states is bitwise the same."""
     prec = nb.NB_FP64 if precision == "fp64" else nb.NB_SPLIT
     t_end = 1 << (L - 2)
-    target = cluster(777, 5)
+    targets = [cluster(777, 5), cluster(9000, 6)]
     others = [cluster(n, 200 + n) for n in (300, 1500, 64, 129)]
     kw = dict(precision=prec, jchunk=256)
-    # alone
-    b1 = make_batch(nb, 777, 1, **kw)
-    j1 = b1.add(target.m, target.x, target.v, t_end)
-    run_to_end(b1)
-    alone = states(b1, [j1])[j1]
-    # mixed: other jobs first so the target sits at a different pool offset, one
-    # other job ends earlier and one is removed mid-run
-    b2 = make_batch(nb, 4096, 8, **kw)
+    alone, b1s = [], []
+    for ic in targets:
+        b1 = make_batch(nb, ic.m.size, 1, **kw)
+        j1 = b1.add(ic.m, ic.x, ic.v, t_end)
+        run_to_end(b1)
+        alone.append(states(b1, [j1])[j1])
+        b1s.append((b1, j1))
+    b2 = make_batch(nb, 16384, 8, **kw)
     oj = [b2.add(ic.m, ic.x, ic.v, t_end if k != 1 else t_end // 2) for k, ic in enumerate(others[:2])]
-    j2 = b2.add(target.m, target.x, target.v, t_end)
-    assert b2.info(j2)[0] != b1.info(j1)[0]
+    j2 = [b2.add(ic.m, ic.x, ic.v, t_end) for ic in targets]
+    for (b1, j1), j in zip(b1s, j2):
+        assert b2.info(j)[0] != b1.info(j1)[0]
     for k in range(5):
         b2.step()
     b2.remove(oj[0])
     b2.add(others[2].m, others[2].x, others[2].v, t_end)
     b2.add(others[3].m, others[3].x, others[3].v, t_end)
     run_to_end(b2)
-    mixed = states(b2, [j2])[j2]
-    for k in alone:
-        assert np.array_equal(alone[k], mixed[k]), k
-    assert sum(b1.energy(j1, t_end)) == sum(b2.energy(j2, t_end))
+    for a, j, (b1, j1) in zip(alone, j2, b1s):
+        mixed = states(b2, [j])[j]
+        for k in a:
+            assert np.array_equal(a[k], mixed[k]), (j, k)
+        assert sum(b1.energy(j1, t_end)) == sum(b2.energy(j, t_end))
 
 
 def test_batch_job_at_a_high_pool_offset(nb):
@@ -314,10 +352,11 @@ def test_run_steps_on_the_null_stream(nb):
 def test_run_steps_equals_single_steps(nb):
     """nb_batch_run (many steps, one wait) gives bitwise the states of the same number
     of nb_batch_step calls, and counts the same interactions."""
-    ics = [cluster(n, 300 + n) for n in (90, 700, 1300)]
+    # 9000 bodies: above 8192, the next block time comes from the previous step's minima
+    ics = [cluster(n, 300 + n) for n in (90, 700, 1300, 9000)]
     t_end = 1 << L
-    b1 = make_batch(nb, 4096, 4)
-    b2 = make_batch(nb, 4096, 4)
+    b1 = make_batch(nb, 12000, 4)
+    b2 = make_batch(nb, 12000, 4)
     j1 = [b1.add(ic.m, ic.x, ic.v, t_end) for ic in ics]
     j2 = [b2.add(ic.m, ic.x, ic.v, t_end) for ic in ics]
     inter1 = 0

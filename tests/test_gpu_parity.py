@@ -106,7 +106,10 @@ def make_sim(nb, n, eps=1e-4, **kw):
 
 # ------------------------------------------------------------------ evaluation --
 SHAPES = [(1, 1, 64, 1), (1, 1, 64, 3), (1, 1, 64, 47), (1, 4, 256, 1), (1, 4, 256, 5),
-          (2, 4, 256, 1), (2, 4, 256, 2), (2, 4, 256, 12)]
+          (2, 4, 256, 1), (2, 4, 256, 2), (2, 4, 256, 12),
+          # the small-set kernel: P bodies per wave on 64 / P lanes, direct or LDS tiles
+          (-1, 1, 0, 1), (-1, 1, 0, 37), (-8, 1, 0, 5), (-2, 1, 64, 3), (-16, 1, 64, 16),
+          (-64, 1, 64, 7), (-4, 1, 0, 24)]
 
 
 @pytest.mark.parametrize("eps", [1e-4, 0.0])
@@ -126,6 +129,54 @@ def test_eval_fp64_every_shape(nb, eps):
             errs = eval_errors(got, ref)
             assert max(errs) <= TOL_EVAL, (cfg, n_act, errs)
     sim.eval_config(None)
+
+
+@pytest.mark.parametrize("n,eps", [(9001, 1e-4), (8192, 0.0), (13 * 768, 1e-4)])
+def test_eval_symmetric_full_set(nb, n, eps):
+    """Every body active (n_act = n >= 8192): the pairwise-symmetric kernel (each pair
+    once, added to both bodies). Ragged n (the last block and its halves partly
+    filled) and n a whole number of blocks; every body within the FP64 bound of the
+    oracle; bitwise the same on a second call; within the bound of the one-sided
+    kernel forced by a launch shape; Newton's third law to round-off."""
+    ic, ap = system(n, 131 + n)
+    sim = make_sim(nb, n, eps=eps)
+    sim.set_state(ic.m, ic.x, ic.v, tick0=0, a=ap)
+    sim.predict(0)
+    idx = np.arange(n, dtype=np.int32)
+    shape = sim.eval_config(None, n)
+    say("symmetric shape", n, shape)
+    assert shape["ipl"] == 0  # the symmetric kernel
+    got = host(sim.evaluate(idx))
+    again = host(sim.evaluate(idx))
+    assert np.array_equal(got, again)
+    ref = oracle.evaluate(ic.m, ic.x, ic.v, ap, eps, idx=idx)
+    errs = eval_errors(got, ref)
+    stats = error_stats(got, ref)
+    say("symmetric", n, eps, "max errors a/j/s/phi", errs, "p50/p99/max", stats)
+    assert max(errs) <= TOL_EVAL, errs
+    # Newton's third law: sum m a = sum m j = sum m s = 0 to round-off of the terms
+    for c0 in (0, 3, 6):
+        tot = (ic.m * got[c0:c0 + 3]).sum(axis=1)
+        scale = (ic.m * np.abs(got[c0:c0 + 3])).sum(axis=1)
+        assert np.all(np.abs(tot) <= 1e-12 * scale), (c0, tot, scale)
+    sim.eval_config((2, 4, 256, 16), n)
+    one = host(sim.evaluate(idx))
+    sim.eval_config(None)
+    assert max(eval_errors(one, ref)) <= TOL_EVAL
+
+
+def test_eval_symmetric_reports_a_bad_index(nb):
+    n = 8192
+    ic, ap = system(n, 141)
+    sim = make_sim(nb, n)
+    sim.set_state(ic.m, ic.x, ic.v, a=ap)
+    sim.predict(0)
+    idx = np.arange(n, dtype=np.int32)
+    idx[100] = n + 5
+    sim.evaluate(idx)
+    with pytest.raises(nb.NBodyError) as e:
+        sim.energy(0)
+    assert e.value.status == 1
 
 
 def test_eval_fp64_xcd_mapping(nb):
@@ -478,11 +529,21 @@ def test_large_system_sampled(nb):
 
 
 # --------------------------------------------------- full-size, sampled outputs --
-@pytest.mark.parametrize("n_act", [1, 64, 1024, 8192, 65536])
-def test_c2_full_size_sampled(nb, n_act):
+@pytest.fixture(scope="module")
+def c2_inputs():
+    """The N = 65536 Plummer sphere (seed 2) with its predicted accelerations taken
+    from the oracle: the first pass of the Hermite start-up (a of every body from x
+    and v), as the N = 65536 sweep workload specifies."""
     n = 65536
     ic = ni.plummer(n, 2)
-    ap = ni.plummer_mean_field_acc(ic.x)
+    first = oracle.evaluate(ic.m, ic.x, ic.v, np.zeros((3, n)), 1e-4)
+    return ic, np.ascontiguousarray(first[0:3])
+
+
+@pytest.mark.parametrize("n_act", [1, 64, 1024, 8192, 65536])
+def test_c2_full_size_sampled(nb, c2_inputs, n_act):
+    n = 65536
+    ic, ap = c2_inputs
     sim = make_sim(nb, n, eps=1e-4)
     sim.set_state(ic.m, ic.x, ic.v, a=ap)
     sim.predict(0)

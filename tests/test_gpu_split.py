@@ -110,27 +110,61 @@ def test_split_c2_full_size_sampled(nb):
     check_split(got[:, pick], ref, env, "c2 n=65536 all active")
 
 
+_C3 = {}
+
+
+def c3_inputs():
+    """The N = 2^20 Kroupa-mass sphere (seed 3), its predicted accelerations (the
+    smooth Plummer field: the oracle's N-body accelerations of 2^20 bodies would take
+    about 10^12 interactions on the host), the 4096-body subsample (seed 33) and the
+    oracle's evaluation of every subsample body (4.3e9 interactions), computed once
+    for both precisions."""
+    if not _C3:
+        n = 1 << 20
+        ic = ni.plummer(n, 3, masses=ni.kroupa_masses(n, 3))
+        ap = ni.plummer_mean_field_acc(ic.x)
+        sub = ni.active_subset(n, 4096, 33)
+        say("c3: oracle evaluation of the 4096-body subsample against 2^20 bodies")
+        ref = oracle.evaluate(ic.m, ic.x, ic.v, ap, 1e-4, idx=sub)
+        _C3.update(ic=ic, ap=ap, sub=sub, ref=ref)
+    return _C3["ic"], _C3["ap"], _C3["sub"], _C3["ref"]
+
+
+def rel_stats(got, ref):
+    """Per-body relative errors of a, j, s (3-vector norms) and phi, with their
+    p50 / p99 / max."""
+    out = {}
+    for lab, c0 in (("a", 0), ("j", 3), ("s", 6)):
+        e = np.linalg.norm(got[c0:c0 + 3] - ref[c0:c0 + 3], axis=0) / np.linalg.norm(ref[c0:c0 + 3], axis=0)
+        out[lab] = e
+    out["phi"] = np.abs(got[9] - ref[9]) / np.abs(ref[9])
+    return out
+
+
 @pytest.mark.parametrize("precision", ["fp64", "split"])
-def test_c3_kroupa_2p20_sampled(nb, precision):
+def test_c3_kroupa_2p20_subsample(nb, precision):
     """N = 2^20 Plummer sphere with Kroupa masses, eps = 1e-4: the 4096-body
-    subsample evaluated against all bodies, 64 of them checked against the oracle."""
-    n = 1 << 20
-    ic = ni.plummer(n, 3, masses=ni.kroupa_masses(n, 3))
-    ap = ni.plummer_mean_field_acc(ic.x)
+    subsample evaluated against all bodies and compared, every body of it, with the
+    oracle (p50 / p99 / max relative error printed). FP64: every body within 1e-13.
+    Split: every body within 1e-4 relative, and 64 of them within the FP32 rounding
+    bound of the split-precision tests."""
+    ic, ap, sub, ref = c3_inputs()
+    n = ic.m.size
     prec = nb.NB_SPLIT if precision == "split" else nb.NB_FP64
     sim = nb.Simulation(n, eps=1e-4, precision=prec)
     sim.set_state(ic.m, ic.x, ic.v, a=ap)
     sim.predict(0)
-    sub = ni.active_subset(n, 4096, 33)
     got = sim.evaluate(sub).cpu().numpy()
-    pick = np.arange(0, 4096, 64)
-    ref = oracle.evaluate(ic.m, ic.x, ic.v, ap, 1e-4, idx=sub[pick])
+    st = rel_stats(got, ref)
+    for lab, e in st.items():
+        say(f"c3 {precision} {lab}: relative error over 4096 bodies p50 {np.median(e):.2e} "
+            f"p99 {np.percentile(e, 99):.2e} max {e.max():.2e}")
     if precision == "fp64":
-        for c0 in (0, 3, 6):
-            d = np.linalg.norm(got[c0:c0 + 3, pick] - ref[c0:c0 + 3], axis=0)
-            rel = d / np.linalg.norm(ref[c0:c0 + 3], axis=0)
-            say("c3 fp64 rel err", c0, f"max {rel.max():.2e}")
-            assert rel.max() <= TOL_FP64
+        for lab, e in st.items():
+            assert e.max() <= TOL_FP64, (lab, e.max())
     else:
+        for lab, e in st.items():
+            assert e.max() <= 1e-4, (lab, e.max())
+        pick = np.arange(0, 4096, 64)
         env = envelope(ic.m, ic.x, ic.v, ap, 1e-4, sub[pick], chunk=1 << 16)
-        check_split(got[:, pick], ref, env, "c3 n=2^20")
+        check_split(got[:, pick], ref[:, pick], env, "c3 n=2^20")

@@ -58,15 +58,20 @@ class FakeBatch:
 
     def run_steps(self, k):
         nact = [0] * self.max_jobs
+        tnext = [0] * self.max_jobs
         err = [0] * self.max_jobs
         inter = 0
         for job, st in self.jobs.items():
+            if st[1] == 13:       # a job of 13 bodies fails in its first step
+                err[job] = 2
+                continue
             done = min(k, st[2])
             st[2] -= done
             inter += done * st[1] * st[1]
             nact[job] = st[1] if st[2] > 0 else 0
+            tnext[job] = -(-st[1] // 100) - st[2]   # block steps taken so far
         self.clock.t += 1e-3 * len(self.jobs)
-        return nact, [0] * self.max_jobs, err, inter, k
+        return nact, tnext, err, inter, k
 
     def get(self, job):
         raise AssertionError("not used")
@@ -121,6 +126,37 @@ def test_a_request_that_can_never_fit_is_reported():
     ex = FakeBatch(1000, 2, clock)
     with pytest.raises(RuntimeError):
         Server(ex, clock=clock, sleep=clock.sleep).run(requests([1001], [0]))
+
+
+def test_failed_requests_are_counted_apart_from_the_latencies():
+    """A failing job leaves at its time to failure; the latency percentiles cover
+    only the completed requests."""
+    clock = FakeClock()
+    ex = FakeBatch(1000, 4, clock)
+    reqs = requests([13, 400, 300], [0, 0, 0])
+    summ = Server(ex, steps_per_call=1, clock=clock, sleep=clock.sleep).run(reqs)
+    assert summ["failed"] == 1 and summ["completed"] == 2
+    assert reqs[0].error == 2
+    ok = sorted(r.latency for r in reqs[1:])
+    assert summ["latency_p50_s"] == pytest.approx(0.5 * (ok[0] + ok[1]))
+    assert summ["latency_max_s"] == ok[1]
+    assert reqs[0].latency < ok[0]
+
+
+def test_trace_records_every_block_step():
+    """With steps_per_call = 1 the server records each job's (block time, n_act) per
+    step; a multi-step call cannot be traced."""
+    clock = FakeClock()
+    ex = FakeBatch(1000, 4, clock)
+    reqs = requests([250, 120], [0, 0.0015])
+    Server(ex, steps_per_call=1, clock=clock, sleep=clock.sleep, trace=True).run(reqs)
+    for r in reqs:
+        steps = -(-r.n // 100)
+        # the last step reports n_act 0 (the job is done), the others n bodies
+        assert [t for t, _ in r.trace] == list(range(1, steps))
+        assert all(k == r.n for _, k in r.trace)
+    with pytest.raises(ValueError):
+        Server(ex, steps_per_call=2, trace=True)
 
 
 def test_percentile_interpolates():
