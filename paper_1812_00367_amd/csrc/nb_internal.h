@@ -109,10 +109,10 @@ hipError_t launch_eval(const Arrays &A, const EvalPlan &P, int64_t n, const int3
                        int64_t n_act, double eps, bool split, double *out, hipStream_t st);
 
 // Evaluation of every body against every body with each pair computed once
-// (nbody_sym.hip): blocks of B bodies, a persistent grid of G workgroups over the
-// units (row block, half block), partial sums in a row buffer and a column buffer
-// (row_slots + col_slots doubles), then a fixed-order reduction into the index order.
-// The geometry (and so the summation order) depends on n and G only.
+// (nbody_sym.hip): blocks of B bodies, a persistent grid of G workgroups claiming
+// units (row block, part of a block) from a counter, partial sums in a row buffer and
+// a column buffer (row_slots + col_slots doubles), then a fixed-order reduction into
+// the index order. The geometry (and so the summation order) depends on n only.
 constexpr int kSymWaves = 4;
 constexpr int kSymGroups = 512;  // workgroups (fixed, so the summation order is too)
 struct SymPlan {
@@ -122,7 +122,7 @@ struct SymPlan {
 SymPlan plan_sym(int64_t n, int G);
 hipError_t launch_eval_sym(const Arrays &A, const SymPlan &P, int64_t n, const int32_t *idx,
                            int64_t n_act, double eps, double *rowbuf, double *colbuf,
-                           double *dst, double *dst2, hipStream_t st);
+                           unsigned *claim, double *dst, double *dst2, hipStream_t st);
 
 hipError_t launch_correct(const Arrays &A, int64_t n, const int32_t *idx, int64_t n_act,
                           int64_t tick, int dt_min_log2, hipStream_t st);

@@ -46,12 +46,14 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 // the pairwise-symmetric kernel when its partial sums fit the partial buffer; the
 // default buffer holds them up to kSymDefaultMaxN bodies.
 constexpr int64_t kSymMinN = 8192;
-constexpr int64_t kSymDefaultMaxN = 131072;
+constexpr int64_t kSymDefaultMaxN = 65536;
 
+// Partial-sum slots (10 doubles each) of the symmetric evaluation: one for its unit
+// counter, then its row and column buffers.
 int64_t sym_slots(int64_t n)
 {
     const nb::SymPlan S = nb::plan_sym(n, nb::kSymGroups);
-    return (S.row_slots + S.col_slots + 9) / 10;
+    return 1 + (S.row_slots + S.col_slots + 9) / 10;
 }
 
 int64_t partial_slots_of(const nb_params *p)
@@ -209,8 +211,9 @@ nb_status do_evaluate(nb_ctx *c, const int32_t *idx, int64_t n_act, double *out)
 {
     if (n_act > 0 && use_sym(c, n_act)) {
         const nb::SymPlan S = nb::plan_sym(c->p.n, nb::kSymGroups);
-        double *rowbuf = c->A.part, *colbuf = c->A.part + S.row_slots;
-        NB_HIP(c, nb::launch_eval_sym(c->A, S, c->p.n, idx, n_act, c->p.eps, rowbuf, colbuf,
+        unsigned *claim = reinterpret_cast<unsigned *>(c->A.part);
+        double *rowbuf = c->A.part + 10, *colbuf = rowbuf + S.row_slots;
+        NB_HIP(c, nb::launch_eval_sym(c->A, S, c->p.n, idx, n_act, c->p.eps, rowbuf, colbuf, claim,
                                       c->A.evalbuf, out, c->st));
     } else if (n_act > 0) {
         const nb::EvalPlan P = make_plan(c, n_act);

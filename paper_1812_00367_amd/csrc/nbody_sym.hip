@@ -19,20 +19,22 @@
 // is (row block I, part of a block): the first P units of row I are the parts of
 // block I itself (taken one-sided: every i of the block against every j of the part,
 // self pair masked), then the parts of the blocks J > I (taken symmetrically). Units
-// are numbered row by row, and workgroup w
-// takes the contiguous units [w U / G, (w+1) U / G), keeping the i-sums of a row in
-// registers across its units. Symmetric units stream the j-range through LDS tiles
-// of 64 records; at step k lane l pairs its bodies with record (l + k) mod 64 of the
-// tile, so within a wave each record is updated by one lane at a time and its
-// running sum moves through LDS (read, add, write back) from lane to lane; each wave
-// has its own sums, added in wave order when the tile is done.
+// are numbered row by row. Workgroup w takes unit w first and then claims the next
+// unit from a counter (consecutive units of one row reuse the row's bodies in
+// registers), so a workgroup that runs ahead of the other on its CU takes more units
+// instead of leaving that one to finish alone at half occupancy. Symmetric units
+// stream the j-range through LDS tiles of 64 records; at step k lane l pairs its
+// bodies with record (l + k) mod 64 of the tile, so within a wave each record is
+// updated by one lane at a time and its running sum moves through LDS (read, add,
+// write back) from lane to lane; each wave has its own sums, added in wave order when
+// the tile is done.
 //
-// Partial sums: the i-sums of row I from workgroup w go to slot w + I of the row
-// buffer (the pairs (w, I) of a monotone staircase have distinct sums); the j-sums of
+// Partial sums: the i-sums of unit u go to slot u of the row buffer; the j-sums of
 // unit (I, J, part p) go to slot (J (J - 1) / 2 + I) P + p of the column buffer. A
-// reduction pass adds, for each body, its row slots in workgroup order and then its
-// column slots in row order, and writes the result in the order of the index list.
-// Every sum has a fixed order, so results are bitwise reproducible.
+// reduction pass adds, for each body, the row slots of its block in unit order and
+// then its column slots in row order, and writes the result in the order of the
+// index list. The slots depend on the unit, not on the workgroup that took it, and
+// every sum has a fixed order, so results are bitwise reproducible.
 #include "nb_internal.h"
 #include "nb_device.h"
 
@@ -61,13 +63,12 @@ __device__ __forceinline__ int64_t row_start(int r, int nb, int P)
     return (int64_t)P * ((int64_t)r * nb - (int64_t)r * (r - 1) / 2);
 }
 
-// Unit u -> (row, col, part); row_hint: a row at or before the unit's (advanced).
-__device__ __forceinline__ SymUnit decode_unit(int64_t u, int nb, int P, int &row_hint)
+// Unit u -> (row, col, part).
+__device__ __forceinline__ SymUnit decode_unit(int64_t u, int nb, int P)
 {
-    int I = row_hint;
+    int I = 0;
     while (row_start(I + 1, nb, P) <= u)
         ++I;
-    row_hint = I;
     const int k = (int)(u - row_start(I, nb, P));
     SymUnit s;
     s.row = I;
@@ -170,7 +171,8 @@ __device__ __forceinline__ void load_row(const double2 *__restrict__ src, int n,
 template <int NW>
 __global__ __launch_bounds__(64 * NW, 2) void k_eval_sym(Arrays A, int n, int nb, int P, int64_t U, int G,
                                                     double eps2, double *__restrict__ rowbuf,
-                                                    double *__restrict__ colbuf)
+                                                    double *__restrict__ colbuf,
+                                                    unsigned *__restrict__ claim)
 {
     constexpr int BS = 64 * NW;
     constexpr int B = BS * kSymIPL;
@@ -182,10 +184,9 @@ __global__ __launch_bounds__(64 * NW, 2) void k_eval_sym(Arrays A, int n, int nb
                                                // 64 consecutive doubles per component
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const double2 *__restrict__ src = reinterpret_cast<const double2 *>(A.jrec);
-    const int w = blockIdx.x;
-    const int64_t u0 = (int64_t)w * U / G, u1 = (int64_t)(w + 1) * U / G;
+    __shared__ int64_t s_next;
     SymBody b[kSymIPL];
-    int row = -1, hint = 0;
+    int row = -1;
     double2 stage[CPT];
     int valid = 0;
     auto gload = [&](int j0) {
@@ -210,8 +211,8 @@ __global__ __launch_bounds__(64 * NW, 2) void k_eval_sym(Arrays A, int n, int nb
             }
         }
     };
-    auto flush_row = [&]() {
-        double *dst = rowbuf + (size_t)(w + row) * 10 * B;
+    auto flush_unit = [&](int64_t u) {
+        double *dst = rowbuf + (size_t)u * 10 * B;
 #pragma unroll
         for (int q = 0; q < kSymIPL; ++q) {
             const int r = q * BS + tid;
@@ -219,20 +220,21 @@ __global__ __launch_bounds__(64 * NW, 2) void k_eval_sym(Arrays A, int n, int nb
 #pragma unroll
                 for (int c = 0; c < 10; ++c)
                     dst[(size_t)c * B + r] = b[q].acc[c];
+#pragma unroll
+            for (int c = 0; c < 10; ++c)
+                b[q].acc[c] = 0.0;
         }
     };
-    for (int64_t u = u0; u < u1; ++u) {
-        const SymUnit su = decode_unit(u, nb, P, hint);
+    for (int64_t u = blockIdx.x; u < U;) {
+        const SymUnit su = decode_unit(u, nb, P);
         if (su.row != row) {
-            if (row >= 0)
-                flush_row();
             row = su.row;
             load_row<BS>(src, n, (int64_t)row * B, b);
         }
         const int jbeg = su.col * B + su.part * H;
         const int jend = min(n, jbeg + H);
-        if (jbeg >= jend)
-            continue;  // a part past the last body (uniform over the workgroup)
+        // a part past the last body has no records: its slot holds zeros
+        if (jbeg < jend) {
         const bool sym = su.col != su.row;
         const int ntiles = (jend - jbeg + kSymTile - 1) / kSymTile;
         __syncthreads();  // the previous unit is done with the tiles
@@ -309,16 +311,21 @@ __global__ __launch_bounds__(64 * NW, 2) void k_eval_sym(Arrays A, int n, int nb
                 __syncthreads();  // the sums are read before the next tile's step 0
             }
         }
+        }
+        flush_unit(u);
+        __syncthreads();  // every thread has read s_next
+        if (tid == 0)
+            s_next = G + (int64_t)atomicAdd(claim, 1u);
+        __syncthreads();
+        u = s_next;
     }
-    if (row >= 0)
-        flush_row();
 }
 
-// Per (index-list entry, component): the row slots of the body's block in workgroup
+// Per (index-list entry, component): the row slots of the body's block in unit
 // order, then its column slots in row order.
 template <int B>
 __global__ __launch_bounds__(256) void k_sym_reduce(Arrays A, int n, const int32_t *__restrict__ idx,
-                                                    int n_act, int P, int64_t U, int G,
+                                                    int n_act, int P,
                                                     const double *__restrict__ rowbuf,
                                                     const double *__restrict__ colbuf,
                                                     double *__restrict__ out, double *__restrict__ out2)
@@ -336,11 +343,9 @@ __global__ __launch_bounds__(256) void k_sym_reduce(Arrays A, int n, const int32
     }
     const int nb = (n + B - 1) / B;
     const int K = i / B, r = i - K * B, part = r / H;
-    auto owner = [&](int64_t u) { return (int)(((u + 1) * G - 1) / U); };
-    const int wf = owner(row_start(K, nb, P)), wl = owner(row_start(K + 1, nb, P) - 1);
     double s = 0.0;
-    for (int w = wf; w <= wl; ++w)
-        s += rowbuf[((size_t)(w + K) * 10 + c) * B + r];
+    for (int64_t u = row_start(K, nb, P); u < row_start(K + 1, nb, P); ++u)
+        s += rowbuf[((size_t)u * 10 + c) * B + r];
     const double *col = colbuf + (size_t)K * (K - 1) / 2 * P * 10 * H + (size_t)part * 10 * H +
                         (size_t)c * H + (r - part * H);
     for (int I = 0; I < K; ++I)
@@ -370,21 +375,24 @@ SymPlan plan_sym(int64_t n, int G)
         }
     P.units = P.parts * pairs;
     P.G = (int)(G < P.units ? G : P.units);
-    P.row_slots = (int64_t)(P.G + P.nb) * 10 * P.B;
+    P.row_slots = P.units * 10 * P.B;
     P.col_slots = (int64_t)P.nb * (P.nb - 1) / 2 * 10 * P.B;
     return P;
 }
 
 hipError_t launch_eval_sym(const Arrays &A, const SymPlan &P, int64_t n, const int32_t *idx,
                            int64_t n_act, double eps, double *rowbuf, double *colbuf,
-                           double *dst, double *dst2, hipStream_t st)
+                           unsigned *claim, double *dst, double *dst2, hipStream_t st)
 {
-    static_assert(kSymWaves * 64 * kSymIPL == 768, "k_sym_reduce is instantiated for B = 768");
+    constexpr int B = kSymWaves * 64 * kSymIPL;
+    hipError_t e = launch_fill_i32(reinterpret_cast<int32_t *>(claim), 0, 1, st);
+    if (e != hipSuccess)
+        return e;
     hipLaunchKernelGGL(k_eval_sym<kSymWaves>, dim3(P.G), dim3(64 * kSymWaves), 0, st, A, (int)n,
-                       P.nb, P.parts, P.units, P.G, eps * eps, rowbuf, colbuf);
+                       P.nb, P.parts, P.units, P.G, eps * eps, rowbuf, colbuf, claim);
     const int64_t count = 10 * n_act;
-    hipLaunchKernelGGL(k_sym_reduce<768>, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st,
-                       A, (int)n, idx, (int)n_act, P.parts, P.units, P.G, rowbuf, colbuf, dst, dst2);
+    hipLaunchKernelGGL(k_sym_reduce<B>, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st,
+                       A, (int)n, idx, (int)n_act, P.parts, rowbuf, colbuf, dst, dst2);
     return hipGetLastError();
 }
 
