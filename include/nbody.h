@@ -94,9 +94,10 @@ typedef struct {
     int32_t flags;        /* 0 or NB_FLAG_START_CRACKLE */
     int64_t partial_slots;/* capacity of the partial-sum buffer in units of 10 doubles
                              (j-split x active body); 0 = default: max(4n, 2^20), raised
-                             for FP64 and 8192 <= n <= 131072 to the
-                             at most (512 + nb) 768 + nb (nb - 1) 384 slots, nb = ceil(n / 768),
-                             that the symmetric full evaluation needs (about n^2 / 1536) */
+                             for FP64 and 8192 <= n <= 65536 to what the symmetric full
+                             evaluation needs: 1 + 768 U + 384 nb (nb - 1) slots with
+                             nb = ceil(n / 768) and U = P nb (nb + 1) / 2 units, P the parts
+                             per block (2 to 12); about n^2 / 500 */
     void *stream;         /* hipStream_t for every launch; NULL = the null stream */
 } nb_params;
 
@@ -186,7 +187,7 @@ nb_status nb_get_predicted(nb_ctx *ctx, double *d_xp, double *d_vp, double *d_ap
  * n predicted bodies (self pair excluded), in the precision chosen at
  * nb_create. In FP64, when every body is active (n_act = n >= 8192) and the
  * partial-sum buffer holds its partial sums (the default capacity does up to
- * n = 131072), each pair is computed once and added to both bodies (the terms are
+ * n = 65536), each pair is computed once and added to both bodies (the terms are
  * antisymmetric in the pair apart from the masses); otherwise each active body sums
  * over all bodies. Both agree with the exact sums to FP64 rounding. The result is kept for nb_correct and, if d_out is not NULL, also
  * written to d_out[10][n_act]. n_act = 0 is a no-op. Asynchronous. */

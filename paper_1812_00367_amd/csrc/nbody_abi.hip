@@ -234,15 +234,17 @@ namespace nb {
 // Launch shapes. The chip has 256 CUs x 4 SIMDs: a launch wants a few waves per
 // SIMD, while the partial-sum traffic (S x n_act x 80 bytes) stays small against
 // the O(n_act n) arithmetic. The built-in tables were picked by
-// paper_1812_00367_amd/tune.py on an MI355X (N = 65536, both precisions) and
-// checked by interleaved timings of the candidates at 1024, 8192 and 65536 active
-// bodies.
+// paper_1812_00367_amd/tune.py on an MI355X (N = 65536, both precisions; the
+// small-set rows from a sweep of 1 ... 1024 active bodies) and checked by
+// interleaved timings of the candidates at 1024, 8192 and 65536 active bodies.
 static const EvalRow kDefaultF64[] = {
     {1, -1, 1, 0, 256},
-    {8, -8, 1, 0, 1024},
-    {64, -16, 1, 64, 2048},
-    {128, 1, 1, 64, 1024},
-    {512, 1, 2, 128, 2048},
+    {2, -2, 1, 0, 512},
+    {5, -2, 1, 0, 1024},
+    {22, -8, 1, 64, 1024},
+    {45, -8, 1, 64, 2048},
+    {362, -16, 1, 64, 2048},
+    {724, -16, 1, 64, 4096},
     {2048, 2, 4, 256, 2048},
     {1 << 30, 2, 4, 256, 8192},
 };

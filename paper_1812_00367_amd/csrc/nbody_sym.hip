@@ -358,8 +358,9 @@ __global__ __launch_bounds__(256) void k_sym_reduce(Arrays A, int n, const int32
 }  // namespace
 
 // Geometry of the symmetric evaluation of n bodies by G workgroups.
-// Parts per block: the fewest (longest units) that still give every workgroup about
-// eight units, so that the static split of the units evens out.
+// Parts per block: the fewest (longest units, fewest row partials) that still give
+// every workgroup about eight units to claim, so that the end of the launch, where
+// the last claimed units finish, is short against the whole.
 SymPlan plan_sym(int64_t n, int G)
 {
     SymPlan P{};
