@@ -178,7 +178,6 @@ __global__ __launch_bounds__(64 * NW, 2) void k_eval_sym(Arrays A, int n, int nb
     constexpr int B = BS * kSymIPL;
     const int H = B / P;                         // records per unit
     constexpr int CH = kSymTile * 5;             // 16-byte chunks per tile
-    constexpr int CPT = (CH + BS - 1) / BS;      // chunks per thread when staging
     __shared__ double2 tile[2][CH];
     __shared__ double jsum[NW][10][kSymTile];  // component-major: a wave's 64 lanes touch
                                                // 64 consecutive doubles per component
@@ -187,29 +186,32 @@ __global__ __launch_bounds__(64 * NW, 2) void k_eval_sym(Arrays A, int n, int nb
     __shared__ int64_t s_next;
     SymBody b[kSymIPL];
     int row = -1;
-    double2 stage[CPT];
-    int valid = 0;
-    auto gload = [&](int j0) {
-        valid = (min(n, j0 + kSymTile) - j0) * 5;
-#pragma unroll
-        for (int c = 0; c < CPT; ++c) {
-            const int ch = c * BS + tid;
-            stage[c] = (ch < CH && ch < valid) ? src[(size_t)j0 * 5 + ch] : make_double2(0.0, 0.0);
+    // A tile of 64 whole records is copied from global memory straight into LDS
+    // (each wave moves 64 chunks of 16 bytes per instruction, no registers held
+    // while the steps run); a tile that ends past the last body is staged through
+    // registers with zero-mass far-away records as padding, before the steps.
+    auto tile_async = [&](int j0, int buf) {
+        const double2 *g = src + (size_t)j0 * 5;
+        for (int c = wave * 64; c < CH; c += BS)
+            __builtin_amdgcn_global_load_lds(g + c + lane,
+                                             (__attribute__((address_space(3))) void *)&tile[buf][c],
+                                             16, 0, 0);
+    };
+    auto tile_padded = [&](int j0, int buf) {
+        const int valid = (min(n, j0 + kSymTile) - j0) * 5;
+        for (int ch = tid; ch < CH; ch += BS) {
+            const bool ok = ch < valid;
+            const double2 v = src[(size_t)j0 * 5 + (ok ? ch : 0)];
+            const int part5 = ch % 5;
+            double2 w;
+            w.x = ok ? v.x : (part5 <= 1 ? kFar : 0.0);
+            w.y = ok ? v.y : (part5 == 0 ? kFar : 0.0);
+            tile[buf][ch] = w;
         }
     };
-    auto lstore = [&](int buf) {
-#pragma unroll
-        for (int c = 0; c < CPT; ++c) {
-            const int ch = c * BS + tid;
-            if (ch < CH) {
-                const bool ok = ch < valid;
-                const int part5 = ch % 5;
-                double2 v;
-                v.x = ok ? stage[c].x : (part5 <= 1 ? kFar : 0.0);
-                v.y = ok ? stage[c].y : (part5 == 0 ? kFar : 0.0);
-                tile[buf][ch] = v;
-            }
-        }
+    auto tile_load = [&](int j0, int buf) {
+        if (j0 + kSymTile <= n)
+            tile_async(j0, buf);
     };
     auto flush_unit = [&](int64_t u) {
         double *dst = rowbuf + (size_t)u * 10 * B;
@@ -238,14 +240,16 @@ __global__ __launch_bounds__(64 * NW, 2) void k_eval_sym(Arrays A, int n, int nb
         const bool sym = su.col != su.row;
         const int ntiles = (jend - jbeg + kSymTile - 1) / kSymTile;
         __syncthreads();  // the previous unit is done with the tiles
-        gload(jbeg);
-        lstore(0);
+        tile_load(jbeg, 0);
+        if (jbeg + kSymTile > n)
+            tile_padded(jbeg, 0);
+        __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
         for (int t = 0; t < ntiles; ++t) {
             const int buf = t & 1;
             const int j0 = jbeg + t * kSymTile;
             if (t + 1 < ntiles)
-                gload(j0 + kSymTile);
+                tile_load(j0 + kSymTile, buf ^ 1);  // the buffer the previous tile used
             const double2 *L = tile[buf];
             if (sym) {
                 // step 0: record `lane` starts its sums in this lane's registers
@@ -290,8 +294,9 @@ __global__ __launch_bounds__(64 * NW, 2) void k_eval_sym(Arrays A, int n, int nb
                         pair_sym<false, true>(b[q], p0, p1, p2, p3, p4, eps2, j0 + r, unused);
                 }
             }
-            if (t + 1 < ntiles)
-                lstore(buf ^ 1);
+            if (t + 1 < ntiles && j0 + 2 * kSymTile > n)
+                tile_padded(j0 + kSymTile, buf ^ 1);
+            __builtin_amdgcn_s_waitcnt(0);  // this wave's copies into the next tile
             __syncthreads();
             if (sym) {
                 // the waves' sums of each record, added in wave order, to this unit's
