@@ -41,17 +41,18 @@ DT_MAX, DT_MIN = -3, -40
 SWEEP = (1, 64, 1024, 8192, 65536)
 METRIC = "pairwise interactions/s (acc+jerk+snap) and % of FP64/FP32 vector peak; p99"
 PEAK_FP32_TFLOPS = 157.3           # the chip's FP32 vector peak (packed instructions)
-# sources of the evaluation kernel; the traffic figure below is valid only for them
+# sources of the full-N evaluation kernel (k_eval_sym and the k_sym_reduce pass); the
+# traffic figure below is valid only for them
 KERNEL_SRCS = [os.path.join(ROOT, "paper_1812_00367_amd", "csrc", f)
-               for f in ("nbody_kernels.hip", "nbody_sym.hip", "nb_device.h", "nb_internal.h")]
-# HBM bytes per full-N FP64 evaluation launch from the FETCH_SIZE / WRITE_SIZE runs in
-# profiles/eval_fp64_plummer65536.md, keyed by the sha256 prefix of those sources (a
-# key is moved to a new hash only when the evaluation kernels' gfx950 assembly is
-# unchanged).
-TRAFFIC = {"19f9c23fbeb8fc9a": {"fp64": 2.00 * 21978 * 1024 + 81920 * 1024}}
-# Flops per interaction the evaluation kernels execute (SQ_INSTS_VALU_FLOPS_FP64 /
-# _FP32 x 64 lanes / N^2, same profile), keyed the same way.
-EXECUTED_FLOPS = {"19f9c23fbeb8fc9a": {"fp64": 88.0, "split": 86.0}}
+               for f in ("nbody_sym.hip", "nb_device.h", "nb_internal.h")]
+# HBM bytes per full-N FP64 evaluation launch of k_eval_sym (FETCH_SIZE x 2.00 +
+# WRITE_SIZE x 1.00, both calibrated on a 512 MiB device copy) from
+# profiles/eval_sym_plummer65536.md, keyed by the sha256 prefix of the sources above;
+# any edit of them turns the figure to null until the counters are taken again.
+TRAFFIC = {"53751409a5eceb03": {"fp64": 2.00 * 172751 * 1024 + 1.00 * 777621 * 1024}}
+# FP64 flops per interaction the kernel executes (SQ_INSTS_VALU_FLOPS_FP64 x 64 lanes /
+# N^2, same profile), keyed the same way.
+EXECUTED_FLOPS = {"53751409a5eceb03": {"fp64": 54.9}}
 
 
 def kernel_name(shape, fp64):

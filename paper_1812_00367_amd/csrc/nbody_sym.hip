@@ -31,10 +31,12 @@
 //
 // Partial sums: the i-sums of unit u go to slot u of the row buffer; the j-sums of
 // unit (I, J, part p) go to slot (J (J - 1) / 2 + I) P + p of the column buffer. A
-// reduction pass adds, for each body, the row slots of its block in unit order and
-// then its column slots in row order, and writes the result in the order of the
-// index list. The slots depend on the unit, not on the workgroup that took it, and
-// every sum has a fixed order, so results are bitwise reproducible.
+// reduction pass adds, for each body, the row slots of its block (in unit order,
+// dealt round-robin to four running sums so that their loads overlap) and likewise
+// its column slots (in row order), combines the eight sums in a fixed pattern, and
+// writes the result in the order of the index list. The slots depend on the unit,
+// not on the workgroup that took it, and every sum has a fixed order, so results are
+// bitwise reproducible.
 #include "nb_internal.h"
 #include "nb_device.h"
 
@@ -326,8 +328,8 @@ __global__ __launch_bounds__(64 * NW, 2) void k_eval_sym(Arrays A, int n, int nb
     }
 }
 
-// Per (index-list entry, component): the row slots of the body's block in unit
-// order, then its column slots in row order.
+// Per (index-list entry, component): the row slots of the body's block and its
+// column slots, each in four interleaved running sums, combined in a fixed pattern.
 template <int B>
 __global__ __launch_bounds__(256) void k_sym_reduce(Arrays A, int n, const int32_t *__restrict__ idx,
                                                     int n_act, int P,
@@ -348,13 +350,35 @@ __global__ __launch_bounds__(256) void k_sym_reduce(Arrays A, int n, const int32
     }
     const int nb = (n + B - 1) / B;
     const int K = i / B, r = i - K * B, part = r / H;
-    double s = 0.0;
-    for (int64_t u = row_start(K, nb, P); u < row_start(K + 1, nb, P); ++u)
-        s += rowbuf[((size_t)u * 10 + c) * B + r];
+    // four running sums over slots 0, 1, 2, 3 mod 4 (their loads overlap), added
+    // in a fixed pattern
+    const double *row = rowbuf + ((size_t)row_start(K, nb, P) * 10 + c) * B + r;
+    const int nrow = P * (nb - K);
+    const size_t rs = (size_t)10 * B;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    int k = 0;
+    for (; k + 3 < nrow; k += 4) {
+        s0 += row[k * rs];
+        s1 += row[(k + 1) * rs];
+        s2 += row[(k + 2) * rs];
+        s3 += row[(k + 3) * rs];
+    }
+    for (; k < nrow; ++k)
+        s0 += row[k * rs];
     const double *col = colbuf + (size_t)K * (K - 1) / 2 * P * 10 * H + (size_t)part * 10 * H +
                         (size_t)c * H + (r - part * H);
-    for (int I = 0; I < K; ++I)
-        s += col[(size_t)I * P * 10 * H];
+    const size_t cs = (size_t)P * 10 * H;
+    double t0 = 0.0, t1 = 0.0, t2 = 0.0, t3 = 0.0;
+    int I = 0;
+    for (; I + 3 < K; I += 4) {
+        t0 += col[I * cs];
+        t1 += col[(I + 1) * cs];
+        t2 += col[(I + 2) * cs];
+        t3 += col[(I + 3) * cs];
+    }
+    for (; I < K; ++I)
+        t0 += col[I * cs];
+    const double s = ((s0 + s1) + (s2 + s3)) + ((t0 + t1) + (t2 + t3));
     out[(size_t)c * n_act + q] = s;
     if (out2)
         out2[(size_t)c * n_act + q] = s;
