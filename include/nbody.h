@@ -246,7 +246,7 @@ nb_status nb_set_evaluation(nb_ctx *ctx, const int32_t *d_idx, int64_t n_act,
                             const double *d_in);
 
 /* Launch shape of nb_evaluate, for tuning and tests: h_cfg = {ipl, waves per
- * workgroup, tile, j-splits S (>= 1)}. Two kernel families:
+ * workgroup, tile, j-splits S (>= 1)}. Three kernel families:
  *   - ipl = 1 or 2 active bodies per lane (each lane sweeps every record of its
  *     j-split, read from LDS as wave-wide broadcasts), (waves, tile) one of (1, 64),
  *     (1, 128), (2, 128), (1, 256), (2, 256), (4, 256) with tile the LDS tile in bodies;
@@ -254,12 +254,20 @@ nb_status nb_set_evaluation(nb_ctx *ctx, const int32_t *d_idx, int64_t n_act,
  *     holds P = min(Pmax, the power of two >= n_act) active bodies on 64 / P lanes
  *     each (lane w of a body takes records w, w + 64/P, ... of the split, and the
  *     lane sums are combined by a fixed butterfly); waves 1; tile 64 (LDS tiles of 64
- *     records) or 0 (records read straight from memory).
+ *     records) or 0 (records read straight from memory);
+ *   - FP64 only, the group kernel: ipl = -Pmax with Pmax a power of two <= 128 and
+ *     waves 4 or 8: every wave of a workgroup holds the same group of G = min(Pmax,
+ *     the power of two >= n_act) active bodies (64 / G lanes each; G = 128: two per
+ *     lane) and the waves share the split's records; tile 256 (LDS tiles; raises G to
+ *     at least waves x 64 / 256) or 0 (records read straight from memory). When the
+ *     last workgroup of a group can add the S partial sums cheaply (S x G x 10 at
+ *     most 24 per thread), it does so in the same launch.
  * All zeros (or h_cfg NULL) returns to the launch table. The shape never changes
  * results beyond FP64 rounding of the split sums. Host-only; returns NB_ERR_ARG for an
- * unsupported combination. h_shape_out (may be NULL) receives the shape the next
- * call with n_act bodies will use: {ipl (for the small-set kernel: -P), waves, tile,
- * jchunk, splits, iblocks}. */
+ * unsupported combination. h_shape_out (may be NULL; 7 int32) receives the shape the
+ * next call with n_act bodies will use: {ipl (for the small-set and group kernels:
+ * -P or -G), waves, tile, jchunk, splits, iblocks (groups), fused (1: the splits are
+ * added inside the evaluation launch)}. */
 nb_status nb_eval_config(nb_ctx *ctx, const int32_t *h_cfg, int64_t n_act,
                          int32_t *h_shape_out);
 

@@ -226,11 +226,12 @@ class Simulation:
 
     def eval_config(self, cfg=None, n_act=None):
         """Force (ipl, waves, tile, splits) or restore the default (cfg None); returns the
-        shape {ipl, waves, tile, jchunk, splits, iblocks} used for n_act bodies."""
+        shape {ipl, waves, tile, jchunk, splits, iblocks, fused} used for n_act bodies."""
         arr = (ctypes.c_int32 * 4)(*(cfg if cfg is not None else (0, 0, 0, 0)))
-        shape = (ctypes.c_int32 * 6)()
+        shape = (ctypes.c_int32 * 7)()
         self._check(self._lib.nb_eval_config(self._ctx, arr, int(n_act or self.n), shape))
-        return dict(zip(("ipl", "waves", "tile", "jchunk", "splits", "iblocks"), list(shape)))
+        return dict(zip(("ipl", "waves", "tile", "jchunk", "splits", "iblocks", "fused"),
+                        list(shape)))
 
     def eval_table(self, rows=None):
         """Install a launch-shape table: rows of (n_act_max, ipl, waves, tile, target_waves);

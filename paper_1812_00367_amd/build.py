@@ -18,7 +18,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libnbody.so")
 SOURCES = ["nbody_abi.hip", "nbody_kernels.hip", "nbody_batch.hip", "nbody_crackle.hip",
-           "nbody_sym.hip"]
+           "nbody_sym.hip", "nbody_group.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 

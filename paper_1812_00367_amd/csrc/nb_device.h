@@ -53,6 +53,22 @@ __device__ __forceinline__ int wave_sum_i32(int v)
     return v;
 }
 
+// Workgroup -> (active-body block, j-split). Workgroups are dispatched to the eight
+// XCDs round-robin (workgroup l on XCD l % 8), each XCD with its own L2. When S is a
+// multiple of 8, a 1-D grid is launched and XCD x is given the contiguous splits
+// [x S/8, (x+1) S/8), so each XCD's L2 fetches only its eighth of the j-stream.
+__device__ __forceinline__ void eval_block_coords(int nsplit, int &ib, int &split)
+{
+    if (gridDim.y == 1 && nsplit > 1) {
+        const int l = blockIdx.x, x = l & 7, k = l >> 3, sx = nsplit >> 3;
+        split = x * sx + k % sx;
+        ib = k / sx;
+    } else {
+        ib = blockIdx.x;
+        split = blockIdx.y;
+    }
+}
+
 // Whether any lane of the wave holds an own body with index in [j0, j0 + len): the
 // self pair is masked only on such tiles (wave-uniform decision).
 template <typename B, int IPL>
@@ -283,16 +299,30 @@ __device__ __forceinline__ Rec64 load_rec64(const double2 *__restrict__ src, int
 // Rounds k = 0, 1, ...: lane w takes record jbeg + k W + w. Loads run two rounds
 // ahead. A record past jend is replaced by jbeg's and masked like the self pair (its
 // index set to the lane's own body); masking is used only on rounds that hold the
-// wave's own bodies or the end of the range.
+// wave's own bodies or the end of the range. The first two rounds' records (the
+// head) can be requested early, before the active body's own record is loaded.
+struct DirectHead {
+    Rec64 c, nx;
+};
+
+__device__ __forceinline__ DirectHead direct_head(const double2 *__restrict__ src, int jbeg, int jend,
+                                                  int W, int w)
+{
+    const int rounds = (jend - jbeg + W - 1) / W;
+    auto at = [&](int k) { const int j = jbeg + k * W + w; return j < jend ? j : jbeg; };
+    return DirectHead{load_rec64(src, at(0)), load_rec64(src, at(rounds > 1 ? 1 : 0))};
+}
+
 __device__ __forceinline__ void sweep_direct_f64(const double2 *__restrict__ src, int jbeg, int jend,
-                                                 int W, int w, I64 &b, int lo, int hi, double eps2)
+                                                 int W, int w, I64 &b, int lo, int hi, double eps2,
+                                                 DirectHead h)
 {
     const I64(&one)[1] = reinterpret_cast<const I64(&)[1]>(b);
     const int rounds = (jend - jbeg + W - 1) / W;
     auto idx = [&](int k) { return jbeg + k * W + w; };
     auto at = [&](int k) { const int j = idx(k); return j < jend ? j : jbeg; };
-    Rec64 c = load_rec64(src, at(0));
-    Rec64 nx = load_rec64(src, at(rounds > 1 ? 1 : 0));
+    Rec64 c = h.c;
+    Rec64 nx = h.nx;
     for (int k = 0; k < rounds; ++k) {
         const Rec64 f = load_rec64(src, at(k + 2 < rounds ? k + 2 : k));
         const int r0 = jbeg + k * W;
@@ -305,6 +335,12 @@ __device__ __forceinline__ void sweep_direct_f64(const double2 *__restrict__ src
         c = nx;
         nx = f;
     }
+}
+
+__device__ __forceinline__ void sweep_direct_f64(const double2 *__restrict__ src, int jbeg, int jend,
+                                                 int W, int w, I64 &b, int lo, int hi, double eps2)
+{
+    sweep_direct_f64(src, jbeg, jend, W, w, b, lo, hi, eps2, direct_head(src, jbeg, jend, W, w));
 }
 
 // LDS tiles of 64 records, double-buffered through registers (as the single-system

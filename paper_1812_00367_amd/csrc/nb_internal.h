@@ -46,21 +46,31 @@ struct Arrays {
     Status *status;
     double *jrecj;     // [n][4] predicted jerks {jx, jy, jz, 0} (crackle evaluation)
     double *crk;       // [13][n] start-up crackle pass output, or nullptr
+    unsigned *ectr;    // [kMaxGroups] group counters of the group kernel (zero between
+                       // launches: each launch's last workgroup of a group resets its own)
 };
 
 // Launch shape of one evaluation.
 struct EvalPlan {
-    int ipl;     // active bodies per lane (1, 2); for the small-set kernel, minus the
-                 // active bodies per wave
+    int ipl;     // active bodies per lane (1, 2); for the small-set and group kernels,
+                 // minus the active bodies per wave (group kernel: per workgroup)
     int waves;   // waves per workgroup
-    int tile;    // j-records per LDS tile (0: the small-set kernel reads memory directly)
+    int tile;    // j-records per LDS tile (0: records read from memory directly)
     int jchunk;  // j-records per split (multiple of the tile, or of 64)
     int splits;  // number of j-splits S
-    int iblocks; // workgroups along the active bodies
-    int lw;      // small-set kernel: log2 of the lanes per active body; -1 otherwise
+    int iblocks; // workgroups along the active bodies (groups)
+    int lw;      // small-set and group kernels: log2 of the lanes per active body; -1
+                 // otherwise
+    int fused;   // group kernel with S > 1: the last workgroup of a group adds the S
+                 // partial slots (no separate reduction pass)
 };
 
-constexpr int kLaneTile = 64;  // records per LDS tile of the W-lanes-per-body sweeps
+constexpr int kLaneTile = 64;     // records per LDS tile of the W-lanes-per-body sweeps
+constexpr int kGroupTile = 256;   // records per LDS tile of the group kernel
+constexpr int kMaxGroups = 1 << 16;  // group counters in a workspace
+// The group kernel's in-launch reduction is used when the last workgroup of a group
+// adds at most this many partial values per thread.
+constexpr int kTailPerThread = 24;
 
 constexpr int kActBS = 256;
 constexpr int kActPerThread = 8;
@@ -99,7 +109,11 @@ constexpr int kMaxEvalRows = 32;
 // evenly); or, FP64 only, the small-set kernel: ipl = -Pmax (Pmax in {1, 2, 4, ..., 64}:
 // at most Pmax active bodies per wave, each on 64 / P lanes with P = min(Pmax, the
 // power of two >= n_act)), waves 1, tile 64 (LDS) or 0 (direct from memory).
+// or, FP64 only, the group kernel (nbody_group.hip): ipl = -Pmax with Pmax in {1, 2,
+// 4, ..., 64, 128} (the group's bodies; 128 = two per lane), waves 4 or 8, tile 256
+// (LDS tiles; needs waves x 64 / Pmax <= 256) or 0 (direct reads).
 bool eval_shape_supported(int ipl, int waves, int tile, bool split);
+bool group_shape_ok(int pmax, int waves, int tile);
 // Shape from a table (nrows == 0: the built-in table for the precision).
 EvalPlan plan_eval(int64_t n, int64_t n_act, int64_t partial_slots, bool split,
                    const EvalRow *rows, int nrows);
@@ -107,6 +121,11 @@ EvalPlan plan_eval(int64_t n, int64_t n_act, int64_t partial_slots, bool split,
 EvalPlan plan_eval_fixed(int64_t n, int64_t n_act, int ipl, int waves, int tile, int64_t S);
 hipError_t launch_eval(const Arrays &A, const EvalPlan &P, int64_t n, const int32_t *idx,
                        int64_t n_act, double eps, bool split, double *out, hipStream_t st);
+// The group kernel alone: with S > 1 it writes A.part and, when ctr is given (one
+// zeroed counter per group), reduces them into dst (and dst2) itself.
+hipError_t launch_eval_group(const Arrays &A, const EvalPlan &P, int64_t n, const int32_t *idx,
+                             int64_t n_act, double eps, unsigned *ctr, double *dst, double *dst2,
+                             hipStream_t st);
 
 // Evaluation of every body against every body with each pair computed once
 // (nbody_sym.hip): blocks of B bodies, a persistent grid of G workgroups claiming

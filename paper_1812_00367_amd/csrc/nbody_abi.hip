@@ -104,6 +104,7 @@ size_t layout(const nb_params *p, Arrays *A, char *base)
     A->status = (Status *)take(sizeof(Status));
     A->jrecj = (double *)take(32 * n);
     A->crk = (p->flags & NB_FLAG_START_CRACKLE) ? (double *)take(104 * n) : nullptr;
+    A->ectr = (unsigned *)take(4 * (size_t)nb::kMaxGroups);
     return align256(off);
 }
 
@@ -234,19 +235,17 @@ namespace nb {
 // Launch shapes. The chip has 256 CUs x 4 SIMDs: a launch wants a few waves per
 // SIMD, while the partial-sum traffic (S x n_act x 80 bytes) stays small against
 // the O(n_act n) arithmetic. The built-in tables were picked by
-// paper_1812_00367_amd/tune.py on an MI355X (N = 65536, both precisions; the
-// small-set rows from a sweep of 1 ... 1024 active bodies) and checked by
-// interleaved timings of the candidates at 1024, 8192 and 65536 active bodies.
+// paper_1812_00367_amd/tune.py on an MI355X (N = 65536, both precisions; FP64 from a
+// sweep of 1 ... 32768 active bodies over the broadcast, small-set and group
+// kernels) and checked by timings of the candidates at 1, 64, 1024 and 8192 active
+// bodies.
 static const EvalRow kDefaultF64[] = {
-    {1, -1, 1, 0, 256},
-    {2, -2, 1, 0, 512},
-    {5, -2, 1, 0, 1024},
-    {22, -8, 1, 64, 1024},
-    {45, -8, 1, 64, 2048},
-    {362, -16, 1, 64, 2048},
-    {724, -16, 1, 64, 4096},
-    {2048, 2, 4, 256, 2048},
-    {1 << 30, 2, 4, 256, 8192},
+    {1, -1, 1, 0, 256},     {2, -2, 1, 0, 512},      {5, -4, 4, 0, 1024},
+    {11, -8, 4, 256, 1024}, {22, -16, 8, 256, 2048}, {45, -32, 8, 256, 2048},
+    {90, -32, 8, 256, 4096}, {181, -32, 4, 256, 4096}, {362, -64, 8, 256, 4096},
+    {724, -64, 8, 256, 8192}, {1448, -64, 4, 256, 8192}, {5792, -128, 4, 256, 8192},
+    {11585, -128, 4, 256, 4096},
+    {23170, 2, 1, 64, 8192}, {1 << 30, -128, 4, 256, 16384},
 };
 static const EvalRow kDefaultSplit[] = {
     {128, 1, 1, 64, 1024},
@@ -259,7 +258,11 @@ bool eval_shape_supported(int ipl, int waves, int tile, bool split)
 {
     if (ipl < 0) {
         const int pmax = -ipl;
-        return !split && pmax <= 64 && (pmax & (pmax - 1)) == 0 && waves == 1 &&
+        if (split)
+            return false;
+        if (waves > 1)
+            return group_shape_ok(pmax, waves, tile);
+        return pmax <= 64 && (pmax & (pmax - 1)) == 0 && waves == 1 &&
                (tile == 64 || tile == 0);
     }
     if (ipl != 1 && ipl != 2)
@@ -280,11 +283,38 @@ static void split_range(int64_t n, int64_t S, int unit, EvalPlan &P)
     P.splits = (int)((n + per - 1) / per);
 }
 
+// Group kernel: G = the power of two >= n_act, at most Pmax (and, with LDS tiles, at
+// least 64 waves / 256 so that the lane slots divide a tile); W = 64 / G lanes per
+// body (G = 128: two bodies per lane).
+static void plan_group(int64_t n, int64_t n_act, int pmax, int waves, int tile, int64_t S,
+                       EvalPlan &P)
+{
+    int G = 1;
+    while (G < n_act && G < pmax)
+        G <<= 1;
+    if (tile > 0)
+        while (waves * (64 / (G < 64 ? G : 64)) > kGroupTile)
+            G <<= 1;
+    P.ipl = -G;
+    P.lw = 0;
+    while ((64 >> P.lw) > G)
+        ++P.lw;
+    P.iblocks = (int)((n_act + G - 1) / G);
+    split_range(n, S, tile > 0 ? kGroupTile : 64, P);
+    const int64_t cnt = n_act < G ? n_act : G;
+    P.fused = P.splits > 1 && P.iblocks <= kMaxGroups &&
+              (int64_t)P.splits * cnt * 10 <= (int64_t)kTailPerThread * 64 * waves;
+}
+
 EvalPlan plan_eval_fixed(int64_t n, int64_t n_act, int ipl, int waves, int tile, int64_t S)
 {
     EvalPlan P{};
     P.waves = waves;
     P.tile = tile;
+    if (ipl < 0 && waves > 1) {
+        plan_group(n, n_act, -ipl, waves, tile, S, P);
+        return P;
+    }
     if (ipl < 0) {
         // small-set kernel: P active bodies per wave, 64 / P lanes each
         int pw = 1;
@@ -325,7 +355,7 @@ EvalPlan plan_eval(int64_t n, int64_t n_act, int64_t partial_slots, bool split,
         int64_t pw = 1;
         while (pw < n_act && pw < -r->ipl)
             pw <<= 1;
-        waves_i = (n_act + pw - 1) / pw;
+        waves_i = (n_act + pw - 1) / pw * r->waves;  // group kernel: its waves share a group
     } else {
         const int64_t per_block = (int64_t)r->ipl * 64 * r->waves;
         waves_i = (n_act + per_block - 1) / per_block * r->waves;
@@ -350,8 +380,14 @@ constexpr int kMaxDevices = 64;
 std::mutex g_scratch_mu;
 void *g_scratch_ptr[kMaxDevices];
 
-// The device address of `scratch` on the current device (nullptr on failure).
-void *scratch_on_current_device(hipError_t *err)
+// Layout of the array: the status block, the group kernel's counters (zeroed once per
+// device, then left at zero by every launch), the j-records, the partial sums.
+constexpr size_t kScratchCtrOff = (sizeof(Status) + 255) / 256 * 256;
+constexpr size_t kScratchRecOff = kScratchCtrOff + 4 * (size_t)nb::kMaxGroups;
+
+// The device address of `scratch` on the current device (nullptr on failure). The
+// first call on a device also enqueues the zeroing of the counters on st.
+void *scratch_on_current_device(hipError_t *err, hipStream_t st)
 {
     int dev = -1;
     *err = hipGetDevice(&dev);
@@ -366,6 +402,9 @@ void *scratch_on_current_device(hipError_t *err)
         void *ptr = nullptr;
         *err = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
         if (*err != hipSuccess || !ptr)
+            return nullptr;
+        *err = nb::launch_fill_i32((int32_t *)((char *)ptr + kScratchCtrOff), 0, nb::kMaxGroups, st);
+        if (*err != hipSuccess)
             return nullptr;
         g_scratch_ptr[dev] = ptr;
     }
@@ -416,6 +455,7 @@ nb_status nb_create(const nb_params *p, void *d_workspace, size_t bytes, nb_ctx 
         if (e == hipSuccess) e = nb::launch_fill_f64(q, 0.0, n, c->st);
     for (double *q : {c->A.x, c->A.v, c->A.a, c->A.j, c->A.s, c->A.c})
         if (e == hipSuccess) e = nb::launch_fill_f64(q, 0.0, 3 * n, c->st);
+    if (e == hipSuccess) e = nb::launch_fill_i32((int32_t *)c->A.ectr, 0, nb::kMaxGroups, c->st);
     if (e == hipSuccess) e = nb::launch_fill_i64(c->A.tick, 0, n, c->st);
     if (e == hipSuccess) e = nb::launch_fill_i32(c->A.level, 0, n, c->st);
     if (e == hipSuccess) e = nb::launch_fill_i32((int32_t *)c->A.status, 0, sizeof(Status) / 4, c->st);
@@ -627,17 +667,18 @@ nb_status nb_evaluate_static(int64_t n, const double *d_m, const double *d_xp, c
     const nb::EvalPlan P = nb::plan_eval(n, n_act, partial_slots_of(&dp), false, nullptr, 0);
     const size_t rec_bytes = align256(80 * (size_t)n);
     const size_t part_bytes = P.splits > 1 ? align256(80 * (size_t)P.splits * (size_t)n_act) : 0;
-    const size_t need = align256(sizeof(Status)) + rec_bytes + part_bytes;
+    const size_t need = kScratchRecOff + rec_bytes + part_bytes;
     if (need > NB_STATIC_SCRATCH_BYTES)
         return NB_ERR_SPACE;
     hipError_t e = hipSuccess;
-    char *base = (char *)scratch_on_current_device(&e);
+    hipStream_t st = (hipStream_t)stream;
+    char *base = (char *)scratch_on_current_device(&e, st);
     if (!base)
         return NB_ERR_DEVICE;
-    hipStream_t st = (hipStream_t)stream;
     Arrays A{};
     A.status = (Status *)base;
-    A.jrec = (double *)(base + align256(sizeof(Status)));
+    A.ectr = (unsigned *)(base + kScratchCtrOff);
+    A.jrec = (double *)(base + kScratchRecOff);
     A.part = P.splits > 1 ? (double *)((char *)A.jrec + rec_bytes) : nullptr;
     A.evalbuf = d_out;  // the kernels write (or reduce into) the caller's output
     // the scratch keeps the last call's contents: clear the error words (a fill
@@ -696,6 +737,7 @@ nb_status nb_eval_config(nb_ctx *c, const int32_t *h_cfg, int64_t n_act, int32_t
             h_shape_out[3] = S.B / S.parts;
             h_shape_out[4] = (int32_t)S.units;
             h_shape_out[5] = S.G;
+            h_shape_out[6] = 0;
             return NB_OK;
         }
         const nb::EvalPlan P = make_plan(c, n_act);
@@ -705,6 +747,7 @@ nb_status nb_eval_config(nb_ctx *c, const int32_t *h_cfg, int64_t n_act, int32_t
         h_shape_out[3] = P.jchunk;
         h_shape_out[4] = P.splits;
         h_shape_out[5] = P.iblocks;
+        h_shape_out[6] = P.fused;
     }
     return NB_OK;
 }

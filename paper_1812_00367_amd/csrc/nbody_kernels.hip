@@ -52,22 +52,6 @@ hipError_t fill(T *p, T v, size_t count, hipStream_t st)
     return hipGetLastError();
 }
 
-// Workgroup -> (active-body block, j-split). Workgroups are dispatched to the eight
-// XCDs round-robin (workgroup l on XCD l % 8), each XCD with its own L2. When S is a
-// multiple of 8, a 1-D grid is launched and XCD x is given the contiguous splits
-// [x S/8, (x+1) S/8), so each XCD's L2 fetches only its eighth of the j-stream.
-__device__ __forceinline__ void eval_block_coords(int nsplit, int &ib, int &split)
-{
-    if (gridDim.y == 1 && nsplit > 1) {
-        const int l = blockIdx.x, x = l & 7, k = l >> 3, sx = nsplit >> 3;
-        split = x * sx + k % sx;
-        ib = k / sx;
-    } else {
-        ib = blockIdx.x;
-        split = blockIdx.y;
-    }
-}
-
 // ---------------------------------------------------------------- predictor ----
 // Every body to the block time (predict_body), writing the j-records.
 __global__ __launch_bounds__(256) void k_predict(Arrays A, int n, int64_t tick, double tick_size,
@@ -260,12 +244,18 @@ __global__ __launch_bounds__(64) void k_eval_lanes_f64(Arrays A, int n, const in
     eval_block_coords(nsplit, g, split);
     const int W = 1 << lw, w = (int)threadIdx.x & (W - 1);
     const int slot = (g << (6 - lw)) + ((int)threadIdx.x >> lw);
+    const double2 *__restrict__ src = reinterpret_cast<const double2 *>(A.jrec);
+    const int jbeg = split * jchunk;
+    const int jend = min(n, jbeg + jchunk);
+    // a direct sweep's first records are requested before the active body's record
+    DirectHead head{};
+    if constexpr (DIRECT)
+        head = direct_head(src, jbeg, jend, W, w);
     int i = idx[slot < n_act ? slot : n_act - 1];
     if ((unsigned)i >= (unsigned)n) {
         raise_err(A.status, kErrIndex);
         i = 0;
     }
-    const double2 *__restrict__ src = reinterpret_cast<const double2 *>(A.jrec);
     I64 b;
     {
         const double2 *r = src + (size_t)i * 5;
@@ -279,10 +269,8 @@ __global__ __launch_bounds__(64) void k_eval_lanes_f64(Arrays A, int n, const in
         b.self = i;
     }
     const int lo = wave_min_i32(i), hi = wave_max_i32(i);
-    const int jbeg = split * jchunk;
-    const int jend = min(n, jbeg + jchunk);
     if constexpr (DIRECT)
-        sweep_direct_f64(src, jbeg, jend, W, w, b, lo, hi, eps2);
+        sweep_direct_f64(src, jbeg, jend, W, w, b, lo, hi, eps2, head);
     else
         sweep_lds_f64(src, jbeg, jend, W, lw, w, b, lo, hi, eps2, lds);
 #pragma unroll
@@ -730,7 +718,15 @@ hipError_t launch_eval(const Arrays &A, const EvalPlan &P, int64_t n, const int3
 #define NB_SHAPE(I, W, T)                                                                  \
     else if (P.ipl == I && P.waves == W && P.tile == T) e =                                \
         run_eval<I, W, T>(A, P, n, idx, n_act, eps, split, dst, st);
-    if (P.lw >= 0) {
+    if (P.lw >= 0 && P.waves > 1) {
+        // group kernel: one launch when it reduces the splits itself
+        if (split)
+            return hipErrorInvalidValue;
+        if (P.splits == 1 || P.fused)
+            return launch_eval_group(A, P, n, idx, n_act, eps, P.fused ? A.ectr : nullptr,
+                                     A.evalbuf, out, st);
+        e = launch_eval_group(A, P, n, idx, n_act, eps, nullptr, A.evalbuf, out, st);
+    } else if (P.lw >= 0) {
         if (split)
             return hipErrorInvalidValue;
         const bool xcd = P.splits > 1 && (P.splits % 8) == 0;

@@ -10,6 +10,10 @@ covers active sets up to the geometric midpoint to the next tuned size.
 
 prints the table as JSON (and as a C initializer).
 
+    python -m paper_1812_00367_amd.tune --time-shapes '1024=default,-128/8/256/32'
+
+times the given shapes (interleaved rounds) instead, one JSON line per shape.
+
     python -m paper_1812_00367_amd.tune --batch 128 [--sweep split|factors] [--precision fp64|split]
 
 tunes the batch path instead: it times an ensemble of clusters for each pair of
@@ -31,10 +35,16 @@ SHAPES = [(1, 1, 64), (1, 1, 128), (1, 2, 128), (1, 1, 256), (1, 2, 256), (1, 4,
 # active sets up to SMALL_MAX
 SMALL_SHAPES = [(-p, 1, t) for t in (0, 64) for p in (1, 2, 4, 8, 16, 32, 64)]
 SMALL_MAX = 1024
+# the group kernel (FP64): every wave of a workgroup on one group of at most P active
+# bodies, the waves sharing the split's records from LDS tiles of 256 (all sizes) or
+# read straight from memory (tile 0; timed only up to GROUP_DIRECT_MAX active bodies)
+GROUP_SHAPES = [(-p, w, 256) for w in (4, 8) for p in (2, 4, 8, 16, 32, 64, 128)]
+GROUP_DIRECT = [(-p, w, 0) for w in (4, 8) for p in (1, 2, 4, 8, 16)]
+GROUP_DIRECT_MAX = 64
 TARGETS = [128, 256, 512, 1024, 2048, 4096, 8192, 16384, 32768]
 # active-set sizes up to n / 2: a full set (n_act = n) takes the pairwise-symmetric
 # kernel, which the table does not choose
-DEFAULT_SIZES = [1, 2, 4, 8, 16, 32, 64, 128, 256, 1024, 4096, 16384, 32768]
+DEFAULT_SIZES = [1, 2, 4, 8, 16, 32, 64, 128, 256, 512, 1024, 2048, 4096, 8192, 16384, 32768]
 
 
 def time_eval(sim, idx, out, reps, warm):
@@ -55,7 +65,7 @@ def time_eval(sim, idx, out, reps, warm):
 
 def tune(sim, sizes=None, seed=20, shapes=SHAPES, targets=TARGETS, log=None, small=True):
     """Returns (rows, results); results[n_act] = (best_ms, shape, target, plan).
-    small: also time the small-set kernel's shapes (FP64 contexts only)."""
+    small: also time the small-set and group kernels' shapes (FP64 contexts only)."""
     import torch
 
     import nbody_inputs as ni
@@ -69,12 +79,15 @@ def tune(sim, sizes=None, seed=20, shapes=SHAPES, targets=TARGETS, log=None, sma
         reps = 3 if work > 1e9 else 7
         best = None
         seen = set()
-        cands = list(shapes) + (SMALL_SHAPES if small and na <= SMALL_MAX else [])
+        cands = list(shapes)
+        if small:
+            cands += (SMALL_SHAPES if na <= SMALL_MAX else []) + GROUP_SHAPES
+            cands += GROUP_DIRECT if na <= GROUP_DIRECT_MAX else []
         for shape in cands:
             for tw in targets:
                 sim.eval_table([(1 << 30, *shape, tw)])
                 plan = sim.eval_config(None, na)
-                key = (plan["ipl"], plan["waves"], plan["tile"], plan["splits"])
+                key = (plan["ipl"], plan["waves"], plan["tile"], plan["splits"], plan["fused"])
                 if key in seen:
                     continue
                 seen.add(key)
@@ -152,6 +165,54 @@ def tune_batch(clusters, tick_end, precision, configs, steps_per_call=32, log=No
     return configs[best], rates
 
 
+def parse_shapes(spec):
+    """'1024=default,-128/8/256/32;8192=default' -> {1024: [None, (-128, 8, 256, 32)], ...}"""
+    out = {}
+    for part in filter(None, spec.split(";")):
+        na, cfgs = part.split("=")
+        out[int(na)] = [None if c == "default" else tuple(int(v) for v in c.split("/"))
+                        for c in cfgs.split(",")]
+    return out
+
+
+def time_shapes(sim, cases, rounds=5, reps=3, seed=20, log=print):
+    """Interleaved timing of forced launch shapes (None: the built-in table): for each
+    active-set size, `rounds` passes over its shapes, each timing `reps` calls after one
+    warm-up call; returns and logs the median per shape. Also logs the event time of a
+    one-element add, the floor under any single-launch figure."""
+    import torch
+
+    import nbody_inputs as ni
+    x = torch.zeros(1, dtype=torch.float64, device=sim.device)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(50)]
+    for a, b in ev:
+        a.record()
+        x.add_(1.0)
+        b.record()
+    torch.cuda.synchronize()
+    tiny = sorted(a.elapsed_time(b) for a, b in ev)[25]
+    log(json.dumps({"one_tiny_kernel_event_us": round(tiny * 1e3, 2)}))
+    out = torch.empty((10, sim.n), dtype=torch.float64, device=sim.device)
+    res = []
+    for na, cfgs in cases.items():
+        idx = torch.as_tensor(ni.active_subset(sim.n, na, seed + na), device=sim.device)
+        times = {k: [] for k in range(len(cfgs))}
+        for _ in range(rounds):
+            for k, cfg in enumerate(cfgs):
+                sim.eval_config(cfg, na)
+                times[k].append(time_eval(sim, idx, out, reps, 1))
+        for k, cfg in enumerate(cfgs):
+            shape = sim.eval_config(cfg, na)
+            ms = sorted(times[k])[len(times[k]) // 2]
+            r = {"n_act": na, "cfg": cfg, "us": round(ms * 1e3, 2),
+                 "frac_fp64": round(79.0 * na * sim.n / (ms * 1e-3) / 78.6e12, 4), "shape": shape}
+            res.append(r)
+            log(json.dumps(r))
+    sim.eval_config(None)
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--n", type=int, default=65536)
@@ -164,6 +225,10 @@ def main():
                          "clusters (N log-uniform in [256, 16384], Kroupa masses) to t = 0.125")
     ap.add_argument("--sweep", choices=("split", "factors"), default="split",
                     help="batch: sweep (jchunk, items_per_job) or the item-class chunk factors")
+    ap.add_argument("--time-shapes", default="",
+                    help="time given shapes instead of tuning, e.g. "
+                         "'1024=default,-128/8/256/32;8192=default' (ipl/waves/tile/S)")
+    ap.add_argument("--rounds", type=int, default=5, help="--time-shapes: interleaved passes")
     args = ap.parse_args()
     if args.batch:
         import nbody_inputs as ni
@@ -188,6 +253,10 @@ def main():
                         precision=nb.NB_SPLIT if args.precision == "split" else nb.NB_FP64)
     sim.set_state(ic.m, ic.x, ic.v, a=ni.plummer_mean_field_acc(ic.x))
     sim.predict(0)
+    if args.time_shapes:
+        time_shapes(sim, parse_shapes(args.time_shapes), rounds=args.rounds,
+                    log=lambda m: print(m, flush=True))
+        return
     sizes = [int(v) for v in args.sizes.split(",")] if args.sizes else None
     rows, results = tune(sim, sizes=sizes, log=lambda s: print(s, flush=True),
                          small=args.precision == "fp64")

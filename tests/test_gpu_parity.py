@@ -109,7 +109,11 @@ SHAPES = [(1, 1, 64, 1), (1, 1, 64, 3), (1, 1, 64, 47), (1, 4, 256, 1), (1, 4, 2
           (2, 4, 256, 1), (2, 4, 256, 2), (2, 4, 256, 12),
           # the small-set kernel: P bodies per wave on 64 / P lanes, direct or LDS tiles
           (-1, 1, 0, 1), (-1, 1, 0, 37), (-8, 1, 0, 5), (-2, 1, 64, 3), (-16, 1, 64, 16),
-          (-64, 1, 64, 7), (-4, 1, 0, 24)]
+          (-64, 1, 64, 7), (-4, 1, 0, 24),
+          # the group kernel: every wave of a workgroup on the same G bodies
+          (-128, 8, 256, 1), (-128, 8, 256, 5), (-128, 8, 256, 12), (-128, 4, 256, 3),
+          (-16, 8, 256, 7), (-64, 4, 256, 12), (-2, 8, 256, 6), (-1, 4, 0, 9),
+          (-4, 8, 0, 30), (-32, 8, 256, 40)]
 
 
 @pytest.mark.parametrize("eps", [1e-4, 0.0])
@@ -163,6 +167,71 @@ def test_eval_symmetric_full_set(nb, n, eps):
     one = host(sim.evaluate(idx))
     sim.eval_config(None)
     assert max(eval_errors(one, ref)) <= TOL_EVAL
+
+
+GROUP_SHAPES = [(-128, 8, 256), (-128, 4, 256), (-64, 8, 256), (-16, 8, 256), (-4, 4, 256),
+                (-1, 4, 0), (-2, 8, 0)]
+
+
+@pytest.mark.parametrize("n_act", [1, 3, 64, 333, 1024, 4099])
+def test_eval_group_kernel(nb, n_act):
+    """The group kernel at several split counts, with the splits added by a separate
+    pass or inside the launch (the last workgroup of each group): within the FP64 bound
+    of the oracle, and bitwise the same on a repeated call (the group counters are back
+    at zero after every launch)."""
+    n = 20001
+    ic, ap = system(n, 151)
+    sim = make_sim(nb, n, eps=1e-4)
+    sim.set_state(ic.m, ic.x, ic.v, tick0=0, a=ap)
+    sim.predict(0)
+    idx = ni.active_subset(n, n_act, 152 + n_act)
+    ref = oracle.evaluate(ic.m, ic.x, ic.v, ap, 1e-4, idx=idx)
+    seen = set()
+    for pmax, waves, tile in GROUP_SHAPES:
+        for S in (1, 2, 7, 16, 64):
+            shape = sim.eval_config((pmax, waves, tile, S), n_act)
+            say("group", n_act, (pmax, waves, tile, S), shape)
+            got = host(sim.evaluate(idx))
+            errs = eval_errors(got, ref)
+            assert max(errs) <= TOL_EVAL, (shape, n_act, errs)
+            again = host(sim.evaluate(idx))
+            assert np.array_equal(got, again), shape
+            seen.add((shape["splits"] > 1, shape["fused"]))
+    sim.eval_config(None)
+    # both ways of adding the splits ran (one split only for a single group)
+    assert (True, 1) in seen and (False, 0) in seen, seen
+    if n_act >= 64:
+        assert (True, 0) in seen, seen
+
+
+def test_eval_group_kernel_bad_index_and_xcd_grid(nb):
+    """An index out of range in a group-kernel launch (in-launch reduction) is reported
+    and the next call is correct again; split counts that are multiples of 8 take the
+    XCD-aware 1-D grid."""
+    n = 16284  # 64 tiles of 256, the last one partly filled
+    ic, ap = system(n, 161)
+    sim = make_sim(nb, n)
+    sim.set_state(ic.m, ic.x, ic.v, tick0=0, a=ap)
+    sim.predict(0)
+    idx = ni.active_subset(n, 700, 162)
+    ref = oracle.evaluate(ic.m, ic.x, ic.v, ap, 1e-4, idx=idx)
+    for cfg in [(-128, 8, 256, 8), (-16, 8, 256, 16), (-64, 4, 256, 32)]:
+        shape = sim.eval_config(cfg, len(idx))
+        assert shape["splits"] == cfg[3], shape
+        got = host(sim.evaluate(idx))
+        assert max(eval_errors(got, ref)) <= TOL_EVAL, (cfg, shape)
+    sim.eval_config((-16, 8, 256, 4), 40)
+    assert sim.eval_config((-16, 8, 256, 4), 40)["fused"] == 1
+    bad = np.array(list(range(0, 39)) + [n + 7], np.int32)
+    sim.evaluate(bad)
+    with pytest.raises(nb.NBodyError) as e:
+        sim.energy(0)
+    assert e.value.status == 1
+    good = np.arange(100, 140, dtype=np.int32)
+    got = host(sim.evaluate(good))
+    ref = oracle.evaluate(ic.m, ic.x, ic.v, ap, 1e-4, idx=good)
+    assert max(eval_errors(got, ref)) <= TOL_EVAL
+    sim.eval_config(None)
 
 
 def test_eval_symmetric_reports_a_bad_index(nb):
