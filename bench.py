@@ -452,7 +452,7 @@ def large_workload(n=1 << 20, steps=16):
         subs[name] = sim.evaluate(sub).cpu().numpy()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        inter, tick, done, status, nacts = 0, 0, 0, "ok", []
+        inter, tick, done, status, nacts, levels = 0, 0, 0, "ok", [], []
         for _ in range(steps):
             try:
                 na, tick = sim.step()
@@ -466,8 +466,26 @@ def large_workload(n=1 << 20, steps=16):
                   file=sys.stderr, flush=True)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
-        lv = sim.get_state()["level"]
-        ek, ep = sim.energy(tick) if done else (float("nan"), float("nan"))
+        # the level trajectory, replayed from the same start outside the timed loop: after
+        # each block step the deepest level (smallest step 2^-level) and its body count
+        sim.set_state(ic.m, ic.x, ic.v)
+        sim.start()
+        for _ in range(done):
+            try:
+                sim.step()
+                lvl = sim.get_state()["level"]
+            except nb.NBodyError:
+                break
+            top = int(lvl.max().item())
+            levels.append({"max_level": top, "bodies_at_max": int((lvl == top).sum().item())})
+        try:
+            lv = sim.get_state()["level"]
+            ek, ep = sim.energy(tick) if done else (float("nan"), float("nan"))
+        except nb.NBodyError:
+            # the failed step is reported by the next wait; the deepest level reached
+            # before it is in the trajectory
+            lv = torch.tensor([levels[-1]["max_level"] if levels else -1])
+            ek, ep = float("nan"), float("nan")
         res[name] = {"full_eval_ms": full_ms,
                      "full_eval_interactions_per_s": n * n / (full_ms / 1e3),
                      "block_steps": done, "status": status, "n_act": nacts,
@@ -475,6 +493,7 @@ def large_workload(n=1 << 20, steps=16):
                      "block_steps_interactions_per_s": inter / dt if dt > 0 else None,
                      "time_reached": tick * 2.0 ** DT_MIN,
                      "max_level": int(lv.max().item()),
+                     "level_trajectory": levels,
                      "energy_drift": (ek + ep - e0) / abs(e0)}
         del sim
     d = {}
