@@ -650,38 +650,87 @@ __device__ __forceinline__ void predict_body(const double *X, const double *V, c
 //   a5 = [720 (a1-a0) - 360 h (j1 + j0)     + 60 h^2 (s1 - s0)]    / h^5
 // a3 becomes the crackle of the next prediction; |a4| and |a5| feed the step
 // criterion. Returns false if any result is not finite.
-__device__ __forceinline__ bool correct_body(double *X, double *V, double *Ac, double *Jk, double *S,
-                                             double *C, double *a4n, double *a5n, size_t stride,
-                                             size_t i, const double *e, size_t estride, double h)
+// The corrector from a body's old x, v, a, j, s (k-th component at index k) and the
+// new a, j, s in e[c * estride] (c = 0..8): new x, v, a, j, s, c = a3 and |a4|, |a5|.
+// Returns false if any result is not finite.
+__device__ __forceinline__ bool correct_core(const double (&x0)[3], const double (&v0)[3],
+                                             const double (&a0)[3], const double (&j0)[3],
+                                             const double (&s0)[3], const double *e, size_t estride,
+                                             double h, double (&x1)[3], double (&v1)[3],
+                                             double (&a1)[3], double (&j1)[3], double (&s1)[3],
+                                             double (&d3)[3], double &a4n, double &a5n)
 {
     const double h2 = h * h, h3 = h2 * h, h4 = h3 * h, h5 = h4 * h;
     double a4sq = 0.0, a5sq = 0.0;
     bool finite = true;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-        const size_t o = (size_t)k * stride + i;
-        const double a0 = Ac[o], j0 = Jk[o], s0 = S[o], v0 = V[o], x0 = X[o];
-        const double a1 = e[(size_t)(0 + k) * estride];
-        const double j1 = e[(size_t)(3 + k) * estride];
-        const double s1 = e[(size_t)(6 + k) * estride];
-        const double v1 = v0 + h / 2.0 * (a0 + a1) - h2 / 10.0 * (j1 - j0) + h3 / 120.0 * (s0 + s1);
-        const double x1 = x0 + h / 2.0 * (v0 + v1) - h2 / 10.0 * (a1 - a0) + h3 / 120.0 * (j0 + j1);
-        const double d3 = (60.0 * (a1 - a0) - h * (36.0 * j1 + 24.0 * j0) + h2 * (9.0 * s1 - 3.0 * s0)) / h3;
-        const double d4 =
-            (360.0 * (a1 - a0) - h * (192.0 * j1 + 168.0 * j0) + h2 * (36.0 * s1 - 24.0 * s0)) / h4;
-        const double d5 = (720.0 * (a1 - a0) - 360.0 * h * (j1 + j0) + 60.0 * h2 * (s1 - s0)) / h5;
-        X[o] = x1;
-        V[o] = v1;
-        Ac[o] = a1;
-        Jk[o] = j1;
-        S[o] = s1;
-        C[o] = d3;
+        a1[k] = e[(size_t)(0 + k) * estride];
+        j1[k] = e[(size_t)(3 + k) * estride];
+        s1[k] = e[(size_t)(6 + k) * estride];
+        v1[k] = v0[k] + h / 2.0 * (a0[k] + a1[k]) - h2 / 10.0 * (j1[k] - j0[k]) +
+                h3 / 120.0 * (s0[k] + s1[k]);
+        x1[k] = x0[k] + h / 2.0 * (v0[k] + v1[k]) - h2 / 10.0 * (a1[k] - a0[k]) +
+                h3 / 120.0 * (j0[k] + j1[k]);
+        d3[k] = (60.0 * (a1[k] - a0[k]) - h * (36.0 * j1[k] + 24.0 * j0[k]) +
+                 h2 * (9.0 * s1[k] - 3.0 * s0[k])) / h3;
+        const double d4 = (360.0 * (a1[k] - a0[k]) - h * (192.0 * j1[k] + 168.0 * j0[k]) +
+                           h2 * (36.0 * s1[k] - 24.0 * s0[k])) / h4;
+        const double d5 = (720.0 * (a1[k] - a0[k]) - 360.0 * h * (j1[k] + j0[k]) +
+                           60.0 * h2 * (s1[k] - s0[k])) / h5;
         a4sq += d4 * d4;
         a5sq += d5 * d5;
-        finite = finite && isfinite(x1) && isfinite(v1) && isfinite(d3) && isfinite(d4) && isfinite(d5);
+        finite = finite && isfinite(x1[k]) && isfinite(v1[k]) && isfinite(d3[k]) && isfinite(d4) &&
+                 isfinite(d5);
     }
-    a4n[i] = sqrt(a4sq);
-    a5n[i] = sqrt(a5sq);
+    a4n = sqrt(a4sq);
+    a5n = sqrt(a5sq);
+    return finite;
+}
+
+// A body's old state, for correct_core (component k of body i at k * stride + i).
+struct BodyOld {
+    double x[3], v[3], a[3], j[3], s[3];
+};
+
+__device__ __forceinline__ BodyOld load_body_old(const double *X, const double *V, const double *Ac,
+                                                 const double *Jk, const double *S, size_t stride,
+                                                 size_t i)
+{
+    BodyOld b;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const size_t o = (size_t)k * stride + i;
+        b.x[k] = X[o];
+        b.v[k] = V[o];
+        b.a[k] = Ac[o];
+        b.j[k] = Jk[o];
+        b.s[k] = S[o];
+    }
+    return b;
+}
+
+// The corrector of body i in place, from its stored state (arrays [3][stride]).
+__device__ __forceinline__ bool correct_body(double *X, double *V, double *Ac, double *Jk, double *S,
+                                             double *C, double *a4n, double *a5n, size_t stride,
+                                             size_t i, const double *e, size_t estride, double h)
+{
+    const BodyOld o = load_body_old(X, V, Ac, Jk, S, stride, i);
+    double x1[3], v1[3], a1[3], j1[3], s1[3], d3[3], a4, a5;
+    const bool finite = correct_core(o.x, o.v, o.a, o.j, o.s, e, estride, h, x1, v1, a1, j1, s1, d3,
+                                     a4, a5);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const size_t q = (size_t)k * stride + i;
+        X[q] = x1[k];
+        V[q] = v1[k];
+        Ac[q] = a1[k];
+        Jk[q] = j1[k];
+        S[q] = s1[k];
+        C[q] = d3[k];
+    }
+    a4n[i] = a4;
+    a5n[i] = a5;
     return finite;
 }
 
@@ -695,22 +744,24 @@ __device__ __forceinline__ bool correct_body(double *X, double *V, double *Ac, d
 // the step must also divide t. A body that fits no level up to L is clamped to L
 // and *dtmin is set. Contraction is off and the operation order follows the
 // definition, so the integer level follows from correctly rounded IEEE operations.
-__device__ inline double norm3_nc(const double *p, size_t stride, size_t i)
+__device__ inline double norm3v_nc(double x, double y, double z)
 {
 #pragma clang fp contract(off)
-    const double x = p[i], y = p[stride + i], z = p[2 * stride + i];
     return sqrt(x * x + y * y + z * z);
 }
 
-__device__ inline int level_for_body(const double *Ac, const double *Jk, const double *S,
-                                     const double *C, const double *a4n, const double *a5n,
-                                     size_t stride, size_t i, int64_t t, int kold, int init,
-                                     double eta, double eta_init, int dt_max_log2, int L,
-                                     bool *dtmin)
+__device__ inline double norm3_nc(const double *p, size_t stride, size_t i)
+{
+    return norm3v_nc(p[i], p[stride + i], p[2 * stride + i]);
+}
+
+// The level rules from the norms |a|, |j|, |s|, |a3| and |a4|, |a5| (the last three
+// used by the regular step only).
+__device__ inline int level_from_norms(double an, double jn, double sn, double cn, double a4n,
+                                       double a5n, int64_t t, int kold, int init, double eta,
+                                       double eta_init, int dt_max_log2, int L, bool *dtmin)
 {
 #pragma clang fp contract(off)
-    const double an = norm3_nc(Ac, stride, i), jn = norm3_nc(Jk, stride, i),
-                 sn = norm3_nc(S, stride, i);
     int kc = -1;
     if (init) {
         const double ra = (jn > 0.0) ? an / jn : INFINITY;
@@ -724,9 +775,8 @@ __device__ inline int level_for_body(const double *Ac, const double *Jk, const d
                 break;
             }
     } else {
-        const double cn = norm3_nc(C, stride, i);
         const double num = sqrt(an * sn) + jn;
-        const double den = sqrt(cn * a5n[i]) + a4n[i];
+        const double den = sqrt(cn * a5n) + a4n;
         double qv = INFINITY;
         if (den > 0.0)
             qv = (eta * eta * eta) * (num / den);
@@ -756,6 +806,20 @@ __device__ inline int level_for_body(const double *Ac, const double *Jk, const d
         knew = kold;
     }
     return knew;
+}
+
+// The level of body i from its stored a, j, s, c, |a4|, |a5|.
+__device__ inline int level_for_body(const double *Ac, const double *Jk, const double *S,
+                                     const double *C, const double *a4n, const double *a5n,
+                                     size_t stride, size_t i, int64_t t, int kold, int init,
+                                     double eta, double eta_init, int dt_max_log2, int L,
+                                     bool *dtmin)
+{
+    const double an = norm3_nc(Ac, stride, i), jn = norm3_nc(Jk, stride, i),
+                 sn = norm3_nc(S, stride, i);
+    const double cn = init ? 0.0 : norm3_nc(C, stride, i);
+    return level_from_norms(an, jn, sn, cn, init ? 0.0 : a4n[i], init ? 0.0 : a5n[i], t, kold,
+                            init, eta, eta_init, dt_max_log2, L, dtmin);
 }
 
 }  // namespace nb

@@ -81,6 +81,11 @@ struct Pool {
     // correction; j_mok = 1 when both are up to date
     int64_t *j_mrest, *j_mact;
     int32_t *j_mok;
+    // level-ordered active sets: perm lists each job's bodies by ascending step level
+    // (at off_j), cnt[64 j + l] counts job j's bodies at level l, j_lact is the lowest
+    // level of its last active list and j_lvmode is 1 when the job is kept that way,
+    // 0 when it is scanned instead, -1 before its first active-set pass
+    int32_t *perm, *cnt, *j_lact, *j_lvmode;
     // plan (by position among the stepping jobs)
     int32_t *pl_job, *pl_na, *pl_S, *pl_tiles, *pl_jch;
     int32_t *pl_keep;   // 1: the job keeps its running minima (more than kKnownMinN bodies)
@@ -101,21 +106,339 @@ constexpr int kUnroll = 8;  // bodies per thread per round of the active-set sca
 // previous step instead (smaller ones scan: the bookkeeping would cost more than the
 // round it saves).
 constexpr int64_t kKnownMinN = (int64_t)kUnroll * kBS;
+// Jobs larger than this keep their bodies in level order (bact_levels below): the
+// active-set pass then reads only the last active list, except when that list is
+// longer than kRankMax and the whole order is rebuilt by one workgroup (measured at
+// 26 us for 16384 bodies and 83 us for 65536, against 6-8 us for a short list and
+// about 20 us for the scan of 65536 bodies).
+constexpr int64_t kLevelMinN = 2 * kKnownMinN;
+
+// Active set from the level counts. In the block scheme every body's time t is a
+// multiple of its step dt = 2^(L - level) ticks and the job's time T satisfies
+// t <= T < t + dt, so t = floor(T / dt) dt and all bodies of one level are next due
+// together, at (floor(T / dt) + 1) dt: the next block time is the smallest of these
+// over the occupied levels, and the due bodies are those of every level at or above
+// the lowest due one. perm keeps the job's bodies in the canonical order (level, index)
+// (so the active list, its tail, is the same whatever the job's history, and a job
+// resumed from a checkpoint steps bitwise like the uninterrupted one). After a step
+// only the bodies of the last active list (the tail) have new levels, each one whose
+// step divides the block time, so all above the levels of the other bodies (whose
+// steps do not divide it, or they would have been due): a tail of at most kRankMax
+// bodies is re-sorted in LDS (each body's rank among the tail bodies of its new level
+// with smaller index); a longer one, and a job's first
+// pass, rebuild the whole order by a counting sort over its bodies in index order
+// (each wave a contiguous segment). Every body touched must sit on its level's grid
+// at the job's time; if one does not (a state loaded with unrelated times), the job
+// falls back to the scans (returns false).
+constexpr int kRankMax = kBS;
+constexpr int kGB = 8;  // groups of 64 bodies whose levels a wave loads at once
+
+struct LevelLds {
+    int hist[64];           // bodies per level of the tail (or of the job)
+    int pos[64];            // next position of each level
+    int seg[kBW][64];       // full pass: per wave and level, counts then positions
+    int64_t key[kRankMax + 16];      // tail pass: (level << 32) | index in the job
+    int flag;
+};
+
+// The lanes of the wave whose v (a value in [-1, 63]) equals this lane's: one ballot
+// per bit of v (the value -1 has all bits set, and no lane holds 63 with it in use).
+__device__ __forceinline__ unsigned long long same_value_lanes(int v)
+{
+    unsigned long long m = ~0ull;
+#pragma unroll
+    for (int b = 0; b < 7; ++b) {
+        const bool bit = (v >> b) & 1;
+        const unsigned long long bl = __ballot(bit);
+        m &= bit ? bl : ~bl;
+    }
+    return m;
+}
+
+__device__ __forceinline__ unsigned long long wave_or_u64(unsigned long long v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1)
+        v |= __shfl_xor(v, off, 64);
+    return v;
+}
+
+// The job's scalars, read together at the start of the active-set pass.
+struct JobScalars {
+    int64_t off, n, tnext, tend, nact;
+    int err, lvmode, lact;
+};
+
+__device__ bool bact_levels(const Pool &P, int job, const JobScalars &J, int L, LevelLds &S,
+                            int64_t *red)
+{
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int64_t off = J.off, n = J.n;
+    int32_t *cnt = P.cnt + (size_t)job * 64;
+    const bool full = J.lvmode < 0 || J.nact > kRankMax;
+    const int64_t m = full ? n : J.nact;  // bodies re-sorted: the last active list, or all
+    const int64_t s0 = n - m;             // their first position in perm
+    const int l0 = full ? 0 : J.lact;
+    // the tail's bodies and the old counts are requested before anything waits
+    int id = 0, lv = -1;
+    int64_t tk = 0;
+    if (!full && tid < m) {
+        id = P.act[off + tid];
+        lv = P.level[id];
+        tk = P.tick[id];
+    }
+    const int c_old = (!full && wave == 0) ? cnt[lane] : 0;
+    int64_t tref = J.tnext;
+    if (J.lvmode < 0) {
+        // a job's first pass: its time is its latest body's (a state loaded from a
+        // checkpoint carries the bodies' own times)
+        int64_t t = tref;
+        for (int64_t k = tid; k < n; k += kBS) {
+            const int64_t x = P.tick[off + k];
+            t = x > t ? x : t;
+        }
+        t = -wave_min_i64(-t);
+        if (lane == 0)
+            red[wave] = t;
+        __syncthreads();
+        for (int w = 0; w < kBW; ++w)
+            tref = red[w] > tref ? red[w] : tref;
+        __syncthreads();
+    }
+    auto on_grid = [&](int l, int64_t t) {
+        if (l < 0 || l > L || tref < 0)
+            return false;
+        const int64_t dt = (int64_t)1 << (L - l);
+        return t == tref / dt * dt;
+    };
+    if (tid < 64)
+        S.hist[tid] = 0;
+    for (int e = tid; e < kBW * 64; e += kBS)
+        (&S.seg[0][0])[e] = 0;
+    if (tid == 0)
+        S.flag = 0;
+    __syncthreads();
+    if (full) {
+        // wave w: bodies [w sg, (w + 1) sg) in groups of 64, kGB groups' levels loaded
+        // at once (on the first pass the times are checked too). In a group, the lanes
+        // of one level are found by six ballots (one per bit of the level); the lowest
+        // of them adds the group's count to the wave's counter of that level in LDS
+        const int64_t sg = ((n + kBW - 1) / kBW + 63) / 64 * 64;
+        const int64_t b0 = wave * sg, b1 = min(n, b0 + sg);
+        const bool check = J.lvmode < 0;
+        const unsigned long long below = (1ull << lane) - 1ull;
+        int bad = 0;
+        for (int64_t g0 = b0; g0 < b1; g0 += 64 * kGB) {
+            int l[kGB];
+            int64_t t[kGB];
+#pragma unroll
+            for (int u = 0; u < kGB; ++u) {
+                const int64_t k = g0 + u * 64 + lane;
+                l[u] = k < b1 ? P.level[off + k] : -1;
+                t[u] = (check && k < b1) ? P.tick[off + k] : 0;
+            }
+#pragma unroll
+            for (int u = 0; u < kGB; ++u) {
+                if (l[u] >= 0 && (l[u] > L || (check && !on_grid(l[u], t[u])))) {
+                    bad = 1;
+                    l[u] = -1;
+                }
+                const unsigned long long same = same_value_lanes(l[u]);
+                if (l[u] >= 0 && (same & below) == 0ull)
+                    atomicAdd(&S.seg[wave][l[u]], __popcll(same));
+            }
+        }
+        if (wave_max_i32(bad) && lane == 0)
+            S.flag = 1;
+        __syncthreads();
+        if (S.flag)
+            return false;
+        if (wave == 0) {
+            // level totals, their exclusive prefix, then each wave's start per level
+            int tot = 0;
+            for (int w = 0; w < kBW; ++w)
+                tot += S.seg[w][lane];
+            S.hist[lane] = tot;
+            int incl = tot;
+            for (int o = 1; o < 64; o <<= 1) {
+                const int u = __shfl_up(incl, o, 64);
+                if (lane >= o)
+                    incl += u;
+            }
+            int at = incl - tot;
+            for (int w = 0; w < kBW; ++w) {
+                const int c = S.seg[w][lane];
+                S.seg[w][lane] = at;
+                at += c;
+            }
+        }
+        __syncthreads();
+        for (int64_t g0 = b0; g0 < b1; g0 += 64 * kGB) {
+            int l[kGB];
+#pragma unroll
+            for (int u = 0; u < kGB; ++u) {
+                const int64_t k = g0 + u * 64 + lane;
+                l[u] = k < b1 ? P.level[off + k] : -1;
+            }
+            // the lowest lane of each level takes the group's positions of that level
+            // from the wave's counter (the kGB groups' requests in flight together);
+            // the others read their base from it
+            unsigned long long same[kGB];
+            int base[kGB];
+#pragma unroll
+            for (int u = 0; u < kGB; ++u) {
+                same[u] = same_value_lanes(l[u]);
+                base[u] = 0;
+                if (l[u] >= 0 && (same[u] & below) == 0ull)
+                    base[u] = atomicAdd(&S.seg[wave][l[u]], __popcll(same[u]));
+            }
+#pragma unroll
+            for (int u = 0; u < kGB; ++u) {
+                const int b = __shfl(base[u], __builtin_ctzll(same[u]), 64);
+                if (l[u] >= 0)
+                    P.perm[off + b + __popcll(same[u] & below)] = (int32_t)(g0 + u * 64 + lane + off);
+            }
+        }
+    } else {
+        if (tid < m) {
+            if (on_grid(lv, tk)) {
+                atomicAdd(&S.hist[lv], 1);
+            } else {
+                atomicOr(&S.flag, 1);
+                lv = -1;
+            }
+            S.key[tid] = ((int64_t)lv << 32) | (int64_t)(uint32_t)(id - (int32_t)off);
+        } else if (tid < ((m + 15) & ~15)) {
+            S.key[tid] = INT64_MAX;  // padding of the last group of 16
+        }
+    }
+    __syncthreads();
+    if (wave == 0) {
+        // the counts: below l0 the bodies before the tail (none at l0 or above) plus
+        // the re-sorted bodies' new levels; the next block time; the due levels
+        const int h = S.hist[lane];
+        const int c = lane > L ? 0 : (lane < l0 ? c_old : 0) + h;
+        if (!full) {
+            // the tail must stay behind every other body in level order
+            const int top = wave_max_i32(lane < l0 && c_old > 0 ? lane : -1);
+            const int low = wave_min_i32(h > 0 ? lane : 64);
+            if (lane == 0 && low <= top)
+                S.flag = 1;
+            int incl = h;
+            for (int o = 1; o < 64; o <<= 1) {
+                const int u = __shfl_up(incl, o, 64);
+                if (lane >= o)
+                    incl += u;
+            }
+            S.pos[lane] = (int)s0 + incl - h;
+        }
+        int64_t nx = INT64_MAX;
+        if (c > 0) {
+            const int64_t dt = (int64_t)1 << (L - lane);
+            nx = (tref / dt + 1) * dt;
+        }
+        const int64_t tn = wave_min_i64(nx);
+        const int lmin = wave_min_i32(c > 0 && nx == tn ? lane : 64);
+        const int na = wave_sum_i32(lane >= lmin ? c : 0);
+        if (lane == 0) {
+            red[0] = tn;
+            red[1] = na;
+            red[2] = lmin;
+        }
+        S.hist[lane] = c;  // the new counts, stored below once the pass is known good
+    }
+    __syncthreads();
+    if (S.flag)
+        return false;
+    const int64_t tn = red[0];
+    const int lmin = (int)red[2];
+    const bool skip = tn > J.tend || J.err != kJobOk;
+    const int64_t nact = skip ? 0 : red[1];
+    const int64_t start = n - nact;
+    if (tid < 64)
+        cnt[tid] = S.hist[tid];
+    // act[off + k - start] = perm[off + k] for k in [start, e), eight loads in flight
+    auto copy_due = [&](int64_t e) {
+        for (int64_t k0 = start + tid; k0 < e; k0 += 8 * kBS) {
+            int32_t v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int64_t k = k0 + u * kBS;
+                v[u] = k < e ? P.perm[off + k] : 0;
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int64_t k = k0 + u * kBS;
+                if (k < e)
+                    P.act[off + k - start] = v[u];
+            }
+        }
+    };
+    if (full) {
+        copy_due(n);
+    } else {
+        // bodies before the tail that are due now keep their places in perm
+        copy_due(s0);
+        if (tid < m) {
+            // the tail: rank among the tail bodies of the same level with smaller index,
+            // i.e. the keys in [lv << 32, own key), 16 keys per round
+            const int64_t lo = (int64_t)lv << 32;
+            const int64_t mine = lo | (int64_t)(uint32_t)(id - (int32_t)off);
+            int r = 0;
+            for (int e = 0; e < (int)m; e += 16) {
+#pragma unroll
+                for (int u = 0; u < 16; ++u) {
+                    const int64_t k = S.key[e + u];
+                    r += (k >= lo && k < mine) ? 1 : 0;
+                }
+            }
+            const int64_t at = S.pos[lv] + r;
+            P.perm[off + at] = id;
+            if (at >= start)
+                P.act[off + at - start] = id;
+        }
+    }
+    if (tid == 0) {
+        P.j_tnext[job] = tn;
+        P.j_nact[job] = nact;
+        P.j_lact[job] = skip ? 64 : lmin;
+        P.j_lvmode[job] = 1;
+    }
+    return true;
+}
 
 __global__ __launch_bounds__(kBS) void k_bact(Pool P, const int32_t *__restrict__ jobs, int L)
 {
     __shared__ int64_t red[kBW];
     __shared__ int wcu[kUnroll][kBW];
     __shared__ int sbad[kBW];
+    __shared__ LevelLds s_lev;
     const int job = jobs[blockIdx.x];
+    JobScalars J;
+    J.err = P.j_err[job];
+    J.tnext = P.j_tnext[job];
+    J.tend = P.j_tend[job];
+    J.off = P.j_off[job];
+    J.n = P.j_n[job];
+    J.nact = P.j_nact[job];
+    J.lvmode = P.j_lvmode[job];
+    J.lact = P.j_lact[job];
     // a failed job, or one whose last block time reached its end (every body is then
     // past it), does not step again: no scan
-    if (P.j_err[job] != kJobOk || P.j_tnext[job] >= P.j_tend[job]) {
+    if (J.err != kJobOk || J.tnext >= J.tend) {
         if (threadIdx.x == 0)
             P.j_nact[job] = 0;
         return;
     }
-    const int64_t off = P.j_off[job], n = P.j_n[job];
+    const int64_t off = J.off, n = J.n;
+    if (J.lvmode != 0) {
+        if (bact_levels(P, job, J, L, s_lev, red))
+            return;
+        // the job is scanned from now on (every thread has read j_lvmode)
+        __syncthreads();
+        if (threadIdx.x == 0)
+            P.j_lvmode[job] = 0;
+    }
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     int64_t mn = INT64_MAX;
     int badlevel = 0;
@@ -400,7 +723,7 @@ __device__ __forceinline__ void plan_jobs(const Pool &P, const int32_t *__restri
             P.pl_S[q] = (int32_t)sp.S;
             P.pl_tiles[q] = (int32_t)sp.tiles;
             P.pl_jch[q] = (int32_t)sp.jch;
-            P.pl_keep[q] = n > kKnownMinN ? 1 : 0;
+            P.pl_keep[q] = (n > kKnownMinN && P.j_lvmode[job] == 0) ? 1 : 0;
             for (int k = 0; k < kClasses; ++k)
                 P.pl_item0[k][q] = c_it[k] + x_it[k];
             P.pl_act0[q] = c_act + x_act;
@@ -888,6 +1211,19 @@ __global__ __launch_bounds__(256) void k_bfinish(Pool P, int64_t cap, int mode, 
         const int64_t slot = (live ? e : total - 1) - act0[q], na = P.pl_na[q], pbase = P.pl_pbase[q];
         const int S = P.pl_S[q];
         const bool keep = P.pl_keep[q] != 0;
+        // a step's corrector: the body's index, time, level and old state are requested
+        // before the partial sums, so the two sets of round trips overlap
+        const bool owner = live && l == 0;
+        int64_t i_pre = 0, ti_pre = 0, tn_pre = 0;
+        int kold_pre = 0;
+        BodyOld old{};
+        if (mode == kStep && owner) {
+            i_pre = P.act[P.j_off[job] + slot];
+            old = load_body_old(P.x, P.v, P.a, P.j, P.s, (size_t)cap, (size_t)i_pre);
+            ti_pre = P.tick[i_pre];
+            kold_pre = P.level[i_pre];
+            tn_pre = P.j_tnext[job];
+        }
         double ev[10];
 #pragma unroll
         for (int c = 0; c < 10; ++c)
@@ -940,8 +1276,7 @@ __global__ __launch_bounds__(256) void k_bfinish(Pool P, int64_t cap, int mode, 
         do {
             if (!live || l != 0)
                 break;
-            const int64_t off = P.j_off[job];
-            const int64_t i = P.act[off + slot];
+            const int64_t i = mode == kStep ? i_pre : (int64_t)P.act[P.j_off[job] + slot];
             if (mode == kStartA) {
                 for (int c = 0; c < 3; ++c) {
                     P.jrec[i * kRecD + 6 + c] = ev[c];
@@ -969,17 +1304,43 @@ __global__ __launch_bounds__(256) void k_bfinish(Pool P, int64_t cap, int mode, 
                 if (!finite)  // e.g. two bodies at one place without softening
                     P.j_err[job] = kJobNumeric;
             } else {
-                const int64_t tn = P.j_tnext[job], ti = P.tick[i];
+                // the corrector and the new level from the values in registers
+                const int64_t tn = tn_pre, ti = ti_pre;
                 if (ti >= tn) {
                     P.j_err[job] = kJobLevel;
                     break;
                 }
-                const bool ok = correct_body(P.x, P.v, P.a, P.j, P.s, P.c, P.a4n, P.a5n, (size_t)cap,
-                                             (size_t)i, ev, 1, (double)(tn - ti) * tick_size);
+                double x1[3], v1[3], a1[3], j1[3], s1[3], d3[3], a4, a5;
+                const bool ok = correct_core(old.x, old.v, old.a, old.j, old.s, ev, 1,
+                                             (double)(tn - ti) * tick_size, x1, v1, a1, j1, s1, d3, a4,
+                                             a5);
+                for (int c = 0; c < 3; ++c) {
+                    const size_t o = (size_t)c * cap + i;
+                    P.x[o] = x1[c];
+                    P.v[o] = v1[c];
+                    P.a[o] = a1[c];
+                    P.j[o] = j1[c];
+                    P.s[o] = s1[c];
+                    P.c[o] = d3[c];
+                }
+                P.a4n[i] = a4;
+                P.a5n[i] = a5;
                 P.phi[i] = ev[9];
                 P.tick[i] = tn;
                 if (!ok)
                     P.j_err[job] = kJobNumeric;
+                bool dtmin;
+                const int lv = level_from_norms(norm3v_nc(a1[0], a1[1], a1[2]),
+                                                norm3v_nc(j1[0], j1[1], j1[2]),
+                                                norm3v_nc(s1[0], s1[1], s1[2]),
+                                                norm3v_nc(d3[0], d3[1], d3[2]), a4, a5, tn, kold_pre,
+                                                0, eta, eta_init, dt_max_log2, L, &dtmin);
+                P.level[i] = lv;
+                if (dtmin)
+                    P.j_err[job] = kJobDtMin;
+                if (keep)
+                    nxt = tn + ((int64_t)1 << (L - lv));
+                break;
             }
             bool dtmin;
             const int lv = level_for_body(P.a, P.j, P.s, P.c, P.a4n, P.a5n, (size_t)cap, (size_t)i,
@@ -1021,6 +1382,10 @@ __global__ __launch_bounds__(256) void k_bjob_init(Pool P, int job, int64_t off,
         P.j_tnext[job] = tick0;
         P.j_err[job] = kJobOk;
         P.j_mok[job] = 0;  // the first step scans
+        // a job of more than two scan rounds keeps its bodies in level order (its first
+        // active-set pass sorts them); a smaller one is scanned
+        P.j_lvmode[job] = n > kLevelMinN ? -1 : 0;
+        P.j_lact[job] = 0;
     }
     if (k < n)
         P.act[off + k] = (int32_t)(off + k);
@@ -1223,6 +1588,10 @@ size_t b_layout(const nb_batch_params *p, Pool *P, int32_t **d_jobs, int32_t **d
     P->j_mrest = (int64_t *)take(8 * J);
     P->j_mact = (int64_t *)take(8 * J);
     P->j_mok = (int32_t *)take(4 * J);
+    P->perm = (int32_t *)take(4 * cap);
+    P->cnt = (int32_t *)take(4 * 64 * J);
+    P->j_lact = (int32_t *)take(4 * J);
+    P->j_lvmode = (int32_t *)take(4 * J);
     P->pl_job = (int32_t *)take(4 * J);
     P->pl_na = (int32_t *)take(4 * J);
     P->pl_S = (int32_t *)take(4 * J);
