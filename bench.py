@@ -44,15 +44,15 @@ PEAK_FP32_TFLOPS = 157.3           # the chip's FP32 vector peak (packed instruc
 # sources of the full-N evaluation kernel (k_eval_sym and the k_sym_reduce pass); the
 # traffic figure below is valid only for them
 KERNEL_SRCS = [os.path.join(ROOT, "paper_1812_00367_amd", "csrc", f)
-               for f in ("nbody_sym.hip", "nb_device.h", "nb_internal.h")]
+               for f in ("nbody_sym.hip", "nb_math.h", "nb_internal.h")]
 # HBM bytes per full-N FP64 evaluation launch of k_eval_sym (FETCH_SIZE x 2.00 +
 # WRITE_SIZE x 1.00, both calibrated on a 512 MiB device copy) from
 # profiles/eval_sym_plummer65536.md, keyed by the sha256 prefix of the sources above;
 # any edit of them turns the figure to null until the counters are taken again.
-TRAFFIC = {"53751409a5eceb03": {"fp64": 2.00 * 172751 * 1024 + 1.00 * 777621 * 1024}}
+TRAFFIC = {"5977e8ed1b069f8d": {"fp64": 2.00 * 171595 * 1024 + 1.00 * 777646 * 1024}}
 # FP64 flops per interaction the kernel executes (SQ_INSTS_VALU_FLOPS_FP64 x 64 lanes /
 # N^2, same profile), keyed the same way.
-EXECUTED_FLOPS = {"53751409a5eceb03": {"fp64": 54.9}}
+EXECUTED_FLOPS = {"5977e8ed1b069f8d": {"fp64": 54.9}}
 
 
 def kernel_name(shape, fp64):

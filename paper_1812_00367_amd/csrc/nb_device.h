@@ -7,12 +7,12 @@
 #pragma once
 
 #include "nb_internal.h"
+#include "nb_math.h"
 
 #include <math.h>
 
 namespace nb {
 
-constexpr double kFar = 1.0e18;  // position of the zero-mass records that pad a tile
 
 // ------------------------------------------------------------ wave reductions ----
 __device__ __forceinline__ int64_t wave_min_i64(int64_t v)
@@ -79,19 +79,6 @@ __device__ __forceinline__ bool wave_has_self(const B (&b)[IPL], int j0, int len
     for (int q = 0; q < IPL; ++q)
         mine |= (unsigned)(b[q].self - j0) < (unsigned)len;
     return __ballot(mine) != 0;
-}
-
-// 1/sqrt(x) to about one ulp: the hardware estimate v_rsq_f64 (relative error
-// below 2^-24 measured on gfx950) followed by one third-order correction
-// y (1 + e/2 + 3 e^2 / 8) with e = 1 - x y^2, whose truncation error (5/16) e^3 is
-// far below the FP64 rounding. (An FP32 estimate is as accurate and measured no
-// faster once the conversions are counted.)
-__device__ __forceinline__ double rsqrt_f64(double x)
-{
-    const double y = __builtin_amdgcn_rsq(x);
-    const double e = __builtin_fma(-x, y * y, 1.0);
-    const double p = __builtin_fma(e, 0.375, 0.5);
-    return __builtin_fma(y, e * p, y);
 }
 
 // --------------------------------------------------------- pairwise (FP64) ----

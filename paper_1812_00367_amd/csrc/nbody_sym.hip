@@ -38,7 +38,7 @@
 // not on the workgroup that took it, and every sum has a fixed order, so results are
 // bitwise reproducible.
 #include "nb_internal.h"
-#include "nb_device.h"
+#include "nb_math.h"
 
 namespace nb {
 namespace {
