@@ -517,3 +517,75 @@ def test_c4_full_ensemble_sampled(nb):
             assert np.abs(s1["x"] - ost.x).max() < 1e-12, (step, k)
             assert np.abs(s1["v"] - ost.v).max() < 1e-12, (step, k)
     b.close()
+
+
+# ------------------------------------------------ level-ordered active sets ----
+def test_large_job_resumes_bitwise_from_a_checkpoint(nb):
+    """A job above 16384 bodies keeps its bodies in (level, index) order. Checkpoint it
+    after some steps, admit the checkpoint in a fresh batch (its first active-set pass
+    rebuilds the order from the levels and the latest body time) and step both: the
+    states stay bitwise equal, so the order depends on the levels alone."""
+    ic = cluster(17001, 1201)
+    b = make_batch(nb, 17001, 1)
+    j = b.add(ic.m, ic.x, ic.v, 1 << L)
+    for _ in range(12):
+        b.step()
+    ck = {k: host(t) for k, t in b.get(j).items()}
+    b2 = make_batch(nb, 17001, 1)
+    j2 = b2.add(ck["m"], ck["x"], ck["v"], 1 << L, a=ck["a"], j=ck["j"], s=ck["s"], c=ck["c"],
+                a4n=ck["a4n"], a5n=ck["a5n"], tick=ck["tick"], level=ck["level"])
+    for step in range(20):
+        na1, tn1, e1, _ = b.step()
+        na2, tn2, e2, _ = b2.step()
+        assert e1[j] == 0 and e2[j2] == 0, (step, e1, e2)
+        assert na1[j] == na2[j2] and tn1[j] == tn2[j2], (step, na1[j], na2[j2], tn1[j], tn2[j2])
+    s1 = {k: host(t) for k, t in b.get(j).items()}
+    s2 = {k: host(t) for k, t in b2.get(j2).items()}
+    for k in ("x", "v", "a", "j", "s", "c", "a4n", "a5n", "tick", "level"):
+        assert np.array_equal(s1[k], s2[k]), k
+
+
+def test_large_job_off_its_level_grid_is_scanned(nb):
+    """A job above 16384 bodies loaded with times that are not multiples of their own
+    steps (each body less than one step behind the latest, so that none is due before
+    it) is off its level grid and cannot use the level counts; it falls back to the
+    scans, and every step still advances exactly the oracle's active set at the
+    oracle's block time."""
+    n = 17001
+    ic = cluster(n, 1301)
+    b0 = make_batch(nb, n, 1)
+    j0 = b0.add(ic.m, ic.x, ic.v, 1 << L)  # the Hermite start-up gives a, j, s and levels
+    st0 = {k: host(t) for k, t in b0.get(j0).items()}
+    level = st0["level"]
+    dt = np.int64(1) << (L - level.astype(np.int64))
+    t0 = np.int64(4) << (L - int(level.min()))
+    back = (ni.rng(1302).random(n) * dt).astype(np.int64)  # in [0, dt)
+    back[:: 7] = 0
+    tick = t0 - back
+    assert tick.max() < (tick + dt).min() and np.any(tick % dt != 0)
+    # the start-up state is taken to hold at t0; a body behind is moved back along its
+    # Taylor series, so that the forces the first steps see match its derivatives
+    tau = (-back.astype(np.float64) * 2.0 ** DT_MIN)[None, :]
+    x0, v0, a0, j0, s0 = (st0[k] for k in ("x", "v", "a", "j", "s"))
+    x = x0 + tau * (v0 + tau / 2 * (a0 + tau / 3 * (j0 + tau / 4 * s0)))
+    v = v0 + tau * (a0 + tau / 2 * (j0 + tau / 3 * s0))
+    a = a0 + tau * (j0 + tau / 2 * s0)
+    jj = j0 + tau * s0
+    b = make_batch(nb, n, 1)
+    j = b.add(ic.m, x, v, 1 << (L + 3), a=a, j=jj, s=s0, c=st0["c"],
+              a4n=st0["a4n"], a5n=st0["a5n"], tick=tick, level=level)
+    checked = 0
+    for step in range(10):
+        before = {k: host(t) for k, t in b.get(j).items() if k in ("tick", "level")}
+        nact, tnext, err, _ = b.step()
+        idx, tn = oracle.active(before["tick"], before["level"], L)
+        if err[j] != 0:
+            say("off-grid job: error word", err[j], "at step", step)
+            break  # a start this far from a real orbit may fail; what was taken is checked
+        assert tnext[j] == tn and nact[j] == len(idx), (step, tnext[j], tn, nact[j], len(idx))
+        after = host(b.get(j)["tick"])
+        moved = np.flatnonzero(after != before["tick"]).astype(np.int32)
+        assert np.array_equal(moved, idx), step
+        checked += 1
+    say("off-grid job: steps checked", checked)
+    assert checked >= 3
