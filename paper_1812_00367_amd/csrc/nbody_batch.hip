@@ -10,8 +10,8 @@
 //              prefix sums that place its work items, partial sums and active bodies;
 //   k_beval    persistent waves taking work items (job, i-tile, j-chunk) until none
 //              is left, class after class (three item classes in FP64, two in split);
-//   k_bfinish  four lanes per active body: fixed-order sum of its partials,
-//              corrector, new step level.
+//   k_bfinish  4 to 16 lanes per active body (from the job's S): fixed-order sum of
+//              its partials, corrector, new step level.
 //
 // Pool layout: job j owns the contiguous body range [off_j, off_j + n_j) of a pool of
 // `capacity` bodies; vectors are [3][capacity] structure-of-arrays and the j-records
@@ -52,7 +52,7 @@ enum ItemClass : int { kClassTile = 0, kClassWide = 1, kClassDirect = 2, kClasse
 
 struct StepHdr {
     int64_t nitems[kClasses]; // work items of this step per class
-    int64_t ntotal;       // active bodies of this step (all jobs)
+    int64_t nfinw;        // waves of the finishing pass (each within one job)
     int64_t pslots;       // partial-sum slots used (x 10 doubles)
     int64_t inter;        // interactions accumulated over counted steps
     int64_t steps;        // counted steps in which some job advanced
@@ -89,7 +89,9 @@ struct Pool {
     // plan (by position among the stepping jobs)
     int32_t *pl_job, *pl_na, *pl_S, *pl_tiles, *pl_jch;
     int32_t *pl_keep;   // 1: the job keeps its running minima (more than kKnownMinN bodies)
-    int64_t *pl_item0[kClasses], *pl_act0, *pl_pbase;
+    int64_t *pl_item0[kClasses], *pl_pbase;
+    int64_t *pl_fw0;    // first finishing wave of each stepping job
+    int64_t *pl_off, *pl_n;  // the job's body range (one load less for its work items)
     StepHdr *hdr;
     double *en_bsum;
     Status *status;
@@ -616,6 +618,19 @@ __host__ __device__ inline JobSplit job_split(int64_t n, int64_t na, const Split
     return r;
 }
 
+// Lanes per active body of the finishing pass: a power of two from 4 to 16, the fewest
+// that leave each lane at most eight of the body's S partial sums (one set of loads in
+// flight), 16 above S = 128 (32 or 64 lanes measured no faster: the butterfly grows).
+// A function of S alone, like the sum's order.
+constexpr int kFinMax = 16;
+__host__ __device__ inline int fin_lanes(int64_t S)
+{
+    int f = 4;
+    while (f < kFinMax && 8 * (int64_t)f < S)
+        f <<= 1;
+    return f;
+}
+
 // W lanes per body at or above this read their records straight from global memory
 // (the W lanes of a body read W consecutive records per round, one contiguous
 // block): an LDS tile would give each lane too few records to hide the next tile's
@@ -690,16 +705,17 @@ __device__ __forceinline__ void plan_jobs(const Pool &P, const int32_t *__restri
 {
     constexpr int NW = kPlanBS / 64;
     __shared__ int64_t scr[NW][7], pre[NW + 1][7];
-    int64_t c_plan = 0, c_it[kClasses] = {0, 0, 0}, c_act = 0, c_ps = 0, c_inter = 0;
+    int64_t c_plan = 0, c_it[kClasses] = {0, 0, 0}, c_ps = 0, c_inter = 0, c_fw = 0;
     for (int base = 0; base < njobs; base += kPlanBS) {
         const int p = base + (int)threadIdx.x;
         int job = -1;
-        int64_t na = 0, n = 0;
+        int64_t na = 0, n = 0, off = 0;
         JobSplit sp{0, 0, 0, false};
         if (p < njobs) {
             job = jobs[p];
             na = P.j_nact[job];
             n = P.j_n[job];
+            off = P.j_off[job];
             if (na > 0)
                 sp = job_split(n, na, cfg);
         }
@@ -709,13 +725,15 @@ __device__ __forceinline__ void plan_jobs(const Pool &P, const int32_t *__restri
         const int64_t tail_d = on && !sp.wide && tail_direct(na, sp.tiles) ? 1 : 0;
         const int64_t n_items[kClasses] = {sp.wide ? 0 : (sp.tiles - tail_d) * sp.S,
                                            sp.wide ? sp.tiles * sp.S : 0, tail_d * sp.S};
-        // exclusive prefixes and totals of: stepping jobs, items of each class, active
-        // bodies, partial-sum slots, interactions
-        int64_t x[7] = {on ? 1 : 0, n_items[0], n_items[1], n_items[2], na, sp.S * na, na * n}, t[7];
+        // finishing waves: fin_lanes(S) lanes per active body, a wave within one job
+        const int64_t fw = on ? (na * fin_lanes(sp.S) + 63) / 64 : 0;
+        // exclusive prefixes and totals of: stepping jobs, items of each class,
+        // partial-sum slots, interactions, finishing waves
+        int64_t x[7] = {on ? 1 : 0, n_items[0], n_items[1], n_items[2], sp.S * na, na * n, fw}, t[7];
         block_scan<7, NW>(x, t, scr, pre);
-        const int64_t x_plan = x[0], x_it[kClasses] = {x[1], x[2], x[3]}, x_act = x[4], x_ps = x[5];
-        const int64_t t_plan = t[0], t_it[kClasses] = {t[1], t[2], t[3]}, t_act = t[4], t_ps = t[5],
-                      t_int = t[6];
+        const int64_t x_plan = x[0], x_it[kClasses] = {x[1], x[2], x[3]}, x_ps = x[4], x_fw = x[6];
+        const int64_t t_plan = t[0], t_it[kClasses] = {t[1], t[2], t[3]}, t_ps = t[4], t_int = t[5],
+                      t_fw = t[6];
         if (on) {
             const int64_t q = c_plan + x_plan;
             P.pl_job[q] = job;
@@ -726,15 +744,17 @@ __device__ __forceinline__ void plan_jobs(const Pool &P, const int32_t *__restri
             P.pl_keep[q] = (n > kKnownMinN && P.j_lvmode[job] == 0) ? 1 : 0;
             for (int k = 0; k < kClasses; ++k)
                 P.pl_item0[k][q] = c_it[k] + x_it[k];
-            P.pl_act0[q] = c_act + x_act;
             P.pl_pbase[q] = 10 * (c_ps + x_ps);
+            P.pl_fw0[q] = c_fw + x_fw;
+            P.pl_off[q] = off;
+            P.pl_n[q] = n;
         }
         c_plan += t_plan;
         for (int k = 0; k < kClasses; ++k)
             c_it[k] += t_it[k];
-        c_act += t_act;
         c_ps += t_ps;
         c_inter += t_int;
+        c_fw += t_fw;
     }
     if (threadIdx.x == 0) {
         StepHdr *H = P.hdr;
@@ -745,7 +765,7 @@ __device__ __forceinline__ void plan_jobs(const Pool &P, const int32_t *__restri
             H->nitems[k] = over ? 0 : c_it[k];
             H->counter[k] = 0u;
         }
-        H->ntotal = over ? 0 : c_act;
+        H->nfinw = over ? 0 : c_fw;
         H->pslots = c_ps;
         if (count && !over) {
             H->inter += c_inter;
@@ -864,8 +884,8 @@ __device__ __forceinline__ Item decode_item(const Pool &P, const int64_t *item0,
         it.ibase = (int)(local - (int64_t)it.sp * tiles_a) * kItemTile;
     }
     it.pbase = P.pl_pbase[q];
-    it.off = P.j_off[it.job];
-    it.n = P.j_n[it.job];
+    it.off = P.pl_off[q];
+    it.n = P.pl_n[q];
     const int64_t jch = P.pl_jch[q];
     it.jbeg = (int)(it.off + (int64_t)it.sp * jch);
     it.jend = (int)min(it.off + it.n, (int64_t)it.jbeg + jch);
@@ -1180,36 +1200,35 @@ __global__ __launch_bounds__(64) void k_beval_split(Pool P, float eps2)
 //   kStep:    Hermite corrector over the step, phi and time, new level.
 enum FinishMode : int { kStartA = 0, kStartB = 1, kStep = 2 };
 
-// Four lanes share one active body: a wave takes 16 consecutive active bodies (in
-// the plan's global order), lane l * 16 + b summing chunks l, l + 4, ... of body b in
-// ascending order, so the 16 lanes of each quarter read 16 consecutive slots (128
-// bytes) of one chunk row. The four lane sums are then added by a fixed butterfly
-// (l ^ 2, then l ^ 1), and the lanes with l = 0 apply the result. The order depends
-// on S only.
-constexpr int kFinLanes = 4;
-constexpr int kFinPerWave = 64 / kFinLanes;
-
+// F = fin_lanes(S) lanes share one active body, and each wave of the pass stays within
+// one job: the job's finishing waves (from the plan's prefix) take B = 64 / F of its
+// active bodies each, lane l * B + b summing chunks l, l + F, ... of body b in
+// ascending order, so the B lanes of each group read B consecutive slots of one chunk
+// row. The F lane sums are then added by a fixed butterfly (l ^ F/2, ..., l ^ 1), and
+// the lanes with l = 0 apply the result. The order depends on S only.
 __global__ __launch_bounds__(256) void k_bfinish(Pool P, int64_t cap, int mode, double tick_size,
                                                  double eta, double eta_init, int dt_max_log2, int L)
 {
-    __shared__ int64_t s_act0[kPlanCache];
-    const int64_t total = P.hdr->ntotal;
+    __shared__ int64_t s_fw0[kPlanCache];
+    const int64_t nfw = P.hdr->nfinw;
     const int nplan = P.hdr->nplan;
-    constexpr int per_block = 256 / kFinLanes;
-    if ((int64_t)blockIdx.x * per_block >= total)
+    constexpr int per_block = 256 / 64;
+    if ((int64_t)blockIdx.x * per_block >= nfw)
         return;
-    const int64_t *act0 = cache_prefix(P.pl_act0, nplan, s_act0);
+    const int64_t *fw0 = cache_prefix(P.pl_fw0, nplan, s_fw0);
     const int lane = (int)threadIdx.x & 63;
-    const int l = lane / kFinPerWave, bw = lane % kFinPerWave;
     const int wave = (int)threadIdx.x >> 6;
-    // every lane of a wave runs the same iterations (shuffles inside)
-    for (int64_t e0 = (int64_t)blockIdx.x * per_block; e0 < total; e0 += (int64_t)gridDim.x * per_block) {
-        const int64_t e = e0 + wave * kFinPerWave + bw;
-        const bool live = e < total;
-        const int q = find_entry(act0, nplan, live ? e : total - 1);
+    // a wave-uniform loop over the pass's waves (shuffles inside)
+    for (int64_t gw = (int64_t)blockIdx.x * per_block + wave; gw < nfw; gw += (int64_t)gridDim.x * per_block) {
+        const int q = find_entry(fw0, nplan, gw);
         const int job = P.pl_job[q];
-        const int64_t slot = (live ? e : total - 1) - act0[q], na = P.pl_na[q], pbase = P.pl_pbase[q];
+        const int64_t na = P.pl_na[q], pbase = P.pl_pbase[q];
         const int S = P.pl_S[q];
+        const int F = fin_lanes(S), B = 64 / F;
+        const int l = lane / B;
+        const int64_t want = (gw - fw0[q]) * B + lane % B;
+        const bool live = want < na;
+        const int64_t slot = live ? want : na - 1;
         const bool keep = P.pl_keep[q] != 0;
         // a step's corrector: the body's index, time, level and old state are requested
         // before the partial sums, so the two sets of round trips overlap
@@ -1218,7 +1237,7 @@ __global__ __launch_bounds__(256) void k_bfinish(Pool P, int64_t cap, int mode, 
         int kold_pre = 0;
         BodyOld old{};
         if (mode == kStep && owner) {
-            i_pre = P.act[P.j_off[job] + slot];
+            i_pre = P.act[P.pl_off[q] + slot];
             old = load_body_old(P.x, P.v, P.a, P.j, P.s, (size_t)cap, (size_t)i_pre);
             ti_pre = P.tick[i_pre];
             kold_pre = P.level[i_pre];
@@ -1228,14 +1247,14 @@ __global__ __launch_bounds__(256) void k_bfinish(Pool P, int64_t cap, int mode, 
 #pragma unroll
         for (int c = 0; c < 10; ++c)
             ev[c] = 0.0;
-        // chunks l, l + 4, ... in ascending order; eight (then four) of them are loaded
+        // chunks l, l + F, ... in ascending order; eight (then four) of them are loaded
         // at once so their round trips overlap (the additions keep the one-by-one order)
         int sp = l;
-        for (; sp + 7 * kFinLanes < S; sp += 8 * kFinLanes) {
+        for (; sp + 7 * F < S; sp += 8 * F) {
             double t[8][10];
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
-                const double *src = P.part + pbase + (int64_t)(sp + u * kFinLanes) * 10 * na + slot;
+                const double *src = P.part + pbase + (int64_t)(sp + u * F) * 10 * na + slot;
 #pragma unroll
                 for (int c = 0; c < 10; ++c)
                     t[u][c] = src[(int64_t)c * na];
@@ -1246,11 +1265,11 @@ __global__ __launch_bounds__(256) void k_bfinish(Pool P, int64_t cap, int mode, 
                 for (int c = 0; c < 10; ++c)
                     ev[c] += t[u][c];
         }
-        for (; sp + 3 * kFinLanes < S; sp += 4 * kFinLanes) {
+        for (; sp + 3 * F < S; sp += 4 * F) {
             double t[4][10];
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
-                const double *src = P.part + pbase + (int64_t)(sp + u * kFinLanes) * 10 * na + slot;
+                const double *src = P.part + pbase + (int64_t)(sp + u * F) * 10 * na + slot;
 #pragma unroll
                 for (int c = 0; c < 10; ++c)
                     t[u][c] = src[(int64_t)c * na];
@@ -1261,14 +1280,13 @@ __global__ __launch_bounds__(256) void k_bfinish(Pool P, int64_t cap, int mode, 
                 for (int c = 0; c < 10; ++c)
                     ev[c] += t[u][c];
         }
-        for (; sp < S; sp += kFinLanes) {
+        for (; sp < S; sp += F) {
             const double *src = P.part + pbase + (int64_t)sp * 10 * na + slot;
 #pragma unroll
             for (int c = 0; c < 10; ++c)
                 ev[c] += src[(int64_t)c * na];
         }
-#pragma unroll
-        for (int o = 32; o >= kFinPerWave; o >>= 1)
+        for (int o = 32; o >= B; o >>= 1)
 #pragma unroll
             for (int c = 0; c < 10; ++c)
                 ev[c] += __shfl_xor(ev[c], o, 64);
@@ -1276,7 +1294,7 @@ __global__ __launch_bounds__(256) void k_bfinish(Pool P, int64_t cap, int mode, 
         do {
             if (!live || l != 0)
                 break;
-            const int64_t i = mode == kStep ? i_pre : (int64_t)P.act[P.j_off[job] + slot];
+            const int64_t i = mode == kStep ? i_pre : (int64_t)P.act[P.pl_off[q] + slot];
             if (mode == kStartA) {
                 for (int c = 0; c < 3; ++c) {
                     P.jrec[i * kRecD + 6 + c] = ev[c];
@@ -1354,18 +1372,10 @@ __global__ __launch_bounds__(256) void k_bfinish(Pool P, int64_t cap, int mode, 
         } while (false);
         if (mode == kStep) {
             // the due bodies' new t + dt, reduced per job for the next active-set
-            // pass: a job's bodies are contiguous in plan order, so each job present
-            // in the wave takes one wave minimum and one atomic
-            unsigned long long todo = __ballot(nxt != INT64_MAX);
-            while (todo) {
-                const int lead = __builtin_ctzll(todo);
-                const int jb = __shfl(job, lead, 64);
-                const bool mine = nxt != INT64_MAX && job == jb;
-                const int64_t m = wave_min_i64(mine ? nxt : INT64_MAX);
-                if (lane == lead)
-                    atomicMin(reinterpret_cast<unsigned long long *>(P.j_mact + jb), (unsigned long long)m);
-                todo &= ~__ballot(mine);
-            }
+            // pass: one wave minimum and one atomic (the wave is within one job)
+            const int64_t m = wave_min_i64(nxt);
+            if (lane == 0 && m != INT64_MAX)
+                atomicMin(reinterpret_cast<unsigned long long *>(P.j_mact + job), (unsigned long long)m);
         }
     }
 }
@@ -1452,7 +1462,7 @@ __global__ __launch_bounds__(64) void k_hdr_reset(Pool P)
             H->nitems[k] = 0;
             H->counter[k] = 0u;
         }
-        H->ntotal = 0;
+        H->nfinw = 0;
         H->pslots = 0;
         H->inter = 0;
         H->steps = 0;
@@ -1600,8 +1610,10 @@ size_t b_layout(const nb_batch_params *p, Pool *P, int32_t **d_jobs, int32_t **d
     for (int k = 0; k < nb::kClasses; ++k)
         P->pl_item0[k] = (int64_t *)take(8 * J);
     P->pl_keep = (int32_t *)take(4 * J);
-    P->pl_act0 = (int64_t *)take(8 * J);
     P->pl_pbase = (int64_t *)take(8 * J);
+    P->pl_fw0 = (int64_t *)take(8 * J);
+    P->pl_off = (int64_t *)take(8 * J);
+    P->pl_n = (int64_t *)take(8 * J);
     P->hdr = (nb::StepHdr *)take(sizeof(nb::StepHdr));
     P->en_bsum = (double *)take(16 * (size_t)nb::en_blocks(p->capacity));
     P->status = (nb::Status *)take(sizeof(nb::Status));
