@@ -142,14 +142,15 @@ def test_batch_jobs_match_oracle(nb, factors):
 # ------------------------------------------------------- alone vs mix, bitwise --
 @pytest.mark.parametrize("precision", ["fp64", "split"])
 def test_batch_alone_and_mixed_are_bitwise_equal(nb, precision):
-    """Two target jobs, 777 and 9000 bodies (the larger one above 8192, so after its
-    first step its next block time comes from the previous step's minima instead of
-    a scan), each run alone and then in a mix where they sit at other pool offsets,
-    another job ends earlier, one is removed mid-run and two are admitted later: every
-    field of both targets' final states is bitwise the same."""
+    """Three target jobs, 777, 9000 and 17001 bodies (above 8192 bodies, after its first
+    step a job's next block time comes from the previous step's minima instead of a
+    scan; above 16384 its bodies are kept in level order), each run alone and then in
+    a mix where they sit at other pool offsets, another job ends earlier, one is
+    removed mid-run and two are admitted later: every field of every target's final
+    state is bitwise the same."""
     prec = nb.NB_FP64 if precision == "fp64" else nb.NB_SPLIT
     t_end = 1 << (L - 2)
-    targets = [cluster(777, 5), cluster(9000, 6)]
+    targets = [cluster(777, 5), cluster(9000, 6), cluster(17001, 7)]
     others = [cluster(n, 200 + n) for n in (300, 1500, 64, 129)]
     kw = dict(precision=prec, jchunk=256)
     alone, b1s = [], []
@@ -159,7 +160,7 @@ def test_batch_alone_and_mixed_are_bitwise_equal(nb, precision):
         run_to_end(b1)
         alone.append(states(b1, [j1])[j1])
         b1s.append((b1, j1))
-    b2 = make_batch(nb, 16384, 8, **kw)
+    b2 = make_batch(nb, 32768, 8, **kw)
     oj = [b2.add(ic.m, ic.x, ic.v, t_end if k != 1 else t_end // 2) for k, ic in enumerate(others[:2])]
     j2 = [b2.add(ic.m, ic.x, ic.v, t_end) for ic in targets]
     for (b1, j1), j in zip(b1s, j2):
@@ -352,11 +353,12 @@ def test_run_steps_on_the_null_stream(nb):
 def test_run_steps_equals_single_steps(nb):
     """nb_batch_run (many steps, one wait) gives bitwise the states of the same number
     of nb_batch_step calls, and counts the same interactions."""
-    # 9000 bodies: above 8192, the next block time comes from the previous step's minima
-    ics = [cluster(n, 300 + n) for n in (90, 700, 1300, 9000)]
+    # 9000 bodies: above 8192, the next block time comes from the previous step's
+    # minima; 17001: above 16384, the bodies are kept in level order
+    ics = [cluster(n, 300 + n) for n in (90, 700, 1300, 9000, 17001)]
     t_end = 1 << L
-    b1 = make_batch(nb, 12000, 4)
-    b2 = make_batch(nb, 12000, 4)
+    b1 = make_batch(nb, 30000, 5)
+    b2 = make_batch(nb, 30000, 5)
     j1 = [b1.add(ic.m, ic.x, ic.v, t_end) for ic in ics]
     j2 = [b2.add(ic.m, ic.x, ic.v, t_end) for ic in ics]
     inter1 = 0
