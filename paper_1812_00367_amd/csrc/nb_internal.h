@@ -137,6 +137,10 @@ constexpr int kSymGroups = 512;  // workgroups (fixed, so the summation order is
 struct SymPlan {
     int B, nb, G, parts;  // block size, blocks, workgroups, parts per block
     int64_t units, row_slots, col_slots;
+    // the last units are each cut into `fine` pieces: items (what workgroups claim)
+    // 0 .. split0 - 1 are units 0 .. split0 - 1, then `fine` items per unit
+    int fine;
+    int64_t split0, items;
 };
 SymPlan plan_sym(int64_t n, int G);
 hipError_t launch_eval_sym(const Arrays &A, const SymPlan &P, int64_t n, const int32_t *idx,

@@ -735,7 +735,7 @@ nb_status nb_eval_config(nb_ctx *c, const int32_t *h_cfg, int64_t n_act, int32_t
             h_shape_out[1] = nb::kSymWaves;
             h_shape_out[2] = 64;
             h_shape_out[3] = S.B / S.parts;
-            h_shape_out[4] = (int32_t)S.units;
+            h_shape_out[4] = (int32_t)S.items;
             h_shape_out[5] = S.G;
             h_shape_out[6] = 0;
             return NB_OK;

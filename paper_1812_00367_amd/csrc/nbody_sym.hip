@@ -22,16 +22,20 @@
 // are numbered row by row. Workgroup w takes unit w first and then claims the next
 // unit from a counter (consecutive units of one row reuse the row's bodies in
 // registers), so a workgroup that runs ahead of the other on its CU takes more units
-// instead of leaving that one to finish alone at half occupancy. Symmetric units
+// instead of leaving that one to finish alone at half occupancy. The last units (one
+// per workgroup at most) are each cut into F pieces of H / F records, claimed like
+// units, so that the workgroups' last claims end closer together. Symmetric units
 // stream the j-range through LDS tiles of 64 records; at step k lane l pairs its
 // bodies with record (l + k) mod 64 of the tile, so within a wave each record is
 // updated by one lane at a time and its running sum moves through LDS (read, add,
 // write back) from lane to lane; each wave has its own sums, added in wave order when
-// the tile is done.
+// the tile is done (two sets of sums, used by alternate tiles, so that the next
+// tile's steps start while this tile's sums are being added and stored).
 //
-// Partial sums: the i-sums of unit u go to slot u of the row buffer; the j-sums of
-// unit (I, J, part p) go to slot (J (J - 1) / 2 + I) P + p of the column buffer. A
-// reduction pass adds, for each body, the row slots of its block (in unit order,
+// Partial sums: the i-sums of claimed item v (a unit or a piece) go to slot v of the
+// row buffer; the j-sums of unit (I, J, part p) go to slot (J (J - 1) / 2 + I) P + p
+// of the column buffer (a piece fills its own records of the slot). A
+// reduction pass adds, for each body, the row slots of its block (in item order,
 // dealt round-robin to four running sums so that their loads overlap) and likewise
 // its column slots (in row order), combines the eight sums in a fixed pattern, and
 // writes the result in the order of the index list. The slots depend on the unit,
@@ -63,6 +67,12 @@ struct SymUnit {
 __device__ __forceinline__ int64_t row_start(int r, int nb, int P)
 {
     return (int64_t)P * ((int64_t)r * nb - (int64_t)r * (r - 1) / 2);
+}
+
+// First claimed item of unit u (u = units: the number of items).
+__device__ __forceinline__ int64_t item_of(int64_t u, int64_t split0, int fine)
+{
+    return u <= split0 ? u : split0 + (u - split0) * fine;
 }
 
 // Unit u -> (row, col, part).
@@ -167,12 +177,14 @@ __device__ __forceinline__ void load_row(const double2 *__restrict__ src, int n,
     }
 }
 
-// The symmetric evaluation kernel: a persistent grid of G workgroups over the U units.
+// The symmetric evaluation kernel: a persistent grid of G workgroups over the claimed
+// items (U units, the last of them in pieces).
 // LDS: two j-tiles of 64 records (double-buffered) and, per wave, the running j-sums
-// of the 64 records of the current tile.
+// of the 64 records of a tile (two sets, alternating by tile).
 template <int NW>
-__global__ __launch_bounds__(64 * NW, 2) void k_eval_sym(Arrays A, int n, int nb, int P, int64_t U, int G,
-                                                    double eps2, double *__restrict__ rowbuf,
+__global__ __launch_bounds__(64 * NW, 2) void k_eval_sym(Arrays A, int n, int nb, int P, int64_t split0,
+                                                    int fine, int64_t items, int G, double eps2,
+                                                    double *__restrict__ rowbuf,
                                                     double *__restrict__ colbuf,
                                                     unsigned *__restrict__ claim)
 {
@@ -181,7 +193,7 @@ __global__ __launch_bounds__(64 * NW, 2) void k_eval_sym(Arrays A, int n, int nb
     const int H = B / P;                         // records per unit
     constexpr int CH = kSymTile * 5;             // 16-byte chunks per tile
     __shared__ double2 tile[2][CH];
-    __shared__ double jsum[NW][10][kSymTile];  // component-major: a wave's 64 lanes touch
+    __shared__ double jsum[2][NW][10][kSymTile];  // component-major: a wave's 64 lanes touch
                                                // 64 consecutive doubles per component
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const double2 *__restrict__ src = reinterpret_cast<const double2 *>(A.jrec);
@@ -215,8 +227,8 @@ __global__ __launch_bounds__(64 * NW, 2) void k_eval_sym(Arrays A, int n, int nb
         if (j0 + kSymTile <= n)
             tile_async(j0, buf);
     };
-    auto flush_unit = [&](int64_t u) {
-        double *dst = rowbuf + (size_t)u * 10 * B;
+    auto flush_unit = [&](int64_t slot) {
+        double *dst = rowbuf + (size_t)slot * 10 * B;
 #pragma unroll
         for (int q = 0; q < kSymIPL; ++q) {
             const int r = q * BS + tid;
@@ -229,14 +241,23 @@ __global__ __launch_bounds__(64 * NW, 2) void k_eval_sym(Arrays A, int n, int nb
                 b[q].acc[c] = 0.0;
         }
     };
-    for (int64_t u = blockIdx.x; u < U;) {
+    for (int64_t v = blockIdx.x; v < items;) {
+        // item v: unit u whole, or piece f of F of it
+        int64_t u = v;
+        int f = 0, F = 1;
+        if (v >= split0) {
+            F = fine;
+            u = split0 + (v - split0) / F;
+            f = (int)(v - split0 - (u - split0) * F);
+        }
         const SymUnit su = decode_unit(u, nb, P);
         if (su.row != row) {
             row = su.row;
             load_row<BS>(src, n, (int64_t)row * B, b);
         }
-        const int jbeg = su.col * B + su.part * H;
-        const int jend = min(n, jbeg + H);
+        const int pbeg = su.col * B + su.part * H;  // the part's first record
+        const int jbeg = pbeg + f * (H / F);
+        const int jend = min(n, jbeg + H / F);
         // a part past the last body has no records: its slot holds zeros
         if (jbeg < jend) {
         const bool sym = su.col != su.row;
@@ -267,7 +288,7 @@ __global__ __launch_bounds__(64 * NW, 2) void k_eval_sym(Arrays A, int n, int nb
                         pair_sym<true, false>(b[q], p0, p1, p2, p3, p4, eps2, 0, jac);
 #pragma unroll
                     for (int c = 0; c < 10; ++c)
-                        jsum[wave][c][lane] = jac[c];
+                        jsum[buf][wave][c][lane] = jac[c];
                 }
                 for (int k = 1; k < kSymTile; ++k) {
                     const int r = (lane + k) & (kSymTile - 1);
@@ -276,13 +297,13 @@ __global__ __launch_bounds__(64 * NW, 2) void k_eval_sym(Arrays A, int n, int nb
                     double jac[10];
 #pragma unroll
                     for (int c = 0; c < 10; ++c)
-                        jac[c] = jsum[wave][c][r];
+                        jac[c] = jsum[buf][wave][c][r];
 #pragma unroll
                     for (int q = 0; q < kSymIPL; ++q)
                         pair_sym<true, false>(b[q], p0, p1, p2, p3, p4, eps2, 0, jac);
 #pragma unroll
                     for (int c = 0; c < 10; ++c)
-                        jsum[wave][c][r] = jac[c];
+                        jsum[buf][wave][c][r] = jac[c];
                 }
             } else {
                 // the row's own block: one-sided, self pair masked
@@ -307,24 +328,23 @@ __global__ __launch_bounds__(64 * NW, 2) void k_eval_sym(Arrays A, int n, int nb
                               (((size_t)su.col * (su.col - 1) / 2 + su.row) * P + su.part) * 10 * H;
                 for (int e = tid; e < kSymTile * 10; e += BS) {
                     const int c = e / kSymTile, r = e - c * kSymTile;
-                    double s = jsum[0][c][r];
+                    double s = jsum[buf][0][c][r];
 #pragma unroll
                     for (int v = 1; v < NW; ++v)
-                        s += jsum[v][c][r];
+                        s += jsum[buf][v][c][r];
                     const int j = j0 + r;
                     if (j < jend)
-                        dst[(size_t)c * H + (j - jbeg)] = s;
+                        dst[(size_t)c * H + (j - pbeg)] = s;
                 }
-                __syncthreads();  // the sums are read before the next tile's step 0
             }
         }
         }
-        flush_unit(u);
+        flush_unit(v);
         __syncthreads();  // every thread has read s_next
         if (tid == 0)
             s_next = G + (int64_t)atomicAdd(claim, 1u);
         __syncthreads();
-        u = s_next;
+        v = s_next;
     }
 }
 
@@ -332,7 +352,7 @@ __global__ __launch_bounds__(64 * NW, 2) void k_eval_sym(Arrays A, int n, int nb
 // column slots, each in four interleaved running sums, combined in a fixed pattern.
 template <int B>
 __global__ __launch_bounds__(256) void k_sym_reduce(Arrays A, int n, const int32_t *__restrict__ idx,
-                                                    int n_act, int P,
+                                                    int n_act, int P, int64_t split0, int fine,
                                                     const double *__restrict__ rowbuf,
                                                     const double *__restrict__ colbuf,
                                                     double *__restrict__ out, double *__restrict__ out2)
@@ -352,8 +372,9 @@ __global__ __launch_bounds__(256) void k_sym_reduce(Arrays A, int n, const int32
     const int K = i / B, r = i - K * B, part = r / H;
     // four running sums over slots 0, 1, 2, 3 mod 4 (their loads overlap), added
     // in a fixed pattern
-    const double *row = rowbuf + ((size_t)row_start(K, nb, P) * 10 + c) * B + r;
-    const int nrow = P * (nb - K);
+    const int64_t v0 = item_of(row_start(K, nb, P), split0, fine);
+    const double *row = rowbuf + ((size_t)v0 * 10 + c) * B + r;
+    const int nrow = (int)(item_of(row_start(K + 1, nb, P), split0, fine) - v0);
     const size_t rs = (size_t)10 * B;
     double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
     int k = 0;
@@ -388,8 +409,10 @@ __global__ __launch_bounds__(256) void k_sym_reduce(Arrays A, int n, const int32
 
 // Geometry of the symmetric evaluation of n bodies by G workgroups.
 // Parts per block: the fewest (longest units, fewest row partials) that still give
-// every workgroup about eight units to claim, so that the end of the launch, where
-// the last claimed units finish, is short against the whole.
+// every workgroup about eight units to claim. The last units, as many as there are
+// workgroups and at most a quarter of all, are cut into pieces of 128 records (64
+// when H is not a multiple of 128), so that the end of the launch, where the last
+// claims finish, is short against the whole.
 SymPlan plan_sym(int64_t n, int G)
 {
     SymPlan P{};
@@ -404,8 +427,14 @@ SymPlan plan_sym(int64_t n, int G)
             break;
         }
     P.units = P.parts * pairs;
-    P.G = (int)(G < P.units ? G : P.units);
-    P.row_slots = P.units * 10 * P.B;
+    const int H = P.B / P.parts;
+    P.fine = (H % 128 == 0 && H >= 256) ? H / 128 : (H >= 128 ? H / 64 : 1);
+    int64_t tail = P.fine > 1 ? P.units / 4 : 0;
+    tail = tail < G ? tail : G;
+    P.split0 = P.units - tail;
+    P.items = P.split0 + tail * P.fine;
+    P.G = (int)(G < P.items ? G : P.items);
+    P.row_slots = P.items * 10 * P.B;
     P.col_slots = (int64_t)P.nb * (P.nb - 1) / 2 * 10 * P.B;
     return P;
 }
@@ -419,10 +448,10 @@ hipError_t launch_eval_sym(const Arrays &A, const SymPlan &P, int64_t n, const i
     if (e != hipSuccess)
         return e;
     hipLaunchKernelGGL(k_eval_sym<kSymWaves>, dim3(P.G), dim3(64 * kSymWaves), 0, st, A, (int)n,
-                       P.nb, P.parts, P.units, P.G, eps * eps, rowbuf, colbuf, claim);
+                       P.nb, P.parts, P.split0, P.fine, P.items, P.G, eps * eps, rowbuf, colbuf, claim);
     const int64_t count = 10 * n_act;
     hipLaunchKernelGGL(k_sym_reduce<B>, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st,
-                       A, (int)n, idx, (int)n_act, P.parts, rowbuf, colbuf, dst, dst2);
+                       A, (int)n, idx, (int)n_act, P.parts, P.split0, P.fine, rowbuf, colbuf, dst, dst2);
     return hipGetLastError();
 }
 
