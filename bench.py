@@ -49,10 +49,10 @@ KERNEL_SRCS = [os.path.join(ROOT, "paper_1812_00367_amd", "csrc", f)
 # WRITE_SIZE x 1.00, both calibrated on a 512 MiB device copy) from
 # profiles/eval_sym_plummer65536.md, keyed by the sha256 prefix of the sources above;
 # any edit of them turns the figure to null until the counters are taken again.
-TRAFFIC = {"4a9e6a26361df9aa": {"fp64": 2.00 * 190851 * 1024 + 1.00 * 850923 * 1024}}
+TRAFFIC = {"35b8a367b0d3ebaa": {"fp64": 2.00 * 164221 * 1024 + 1.00 * 693827 * 1024}}
 # FP64 flops per interaction the kernel executes (SQ_INSTS_VALU_FLOPS_FP64 x 64 lanes /
 # N^2, same profile), keyed the same way.
-EXECUTED_FLOPS = {"4a9e6a26361df9aa": {"fp64": 54.9}}
+EXECUTED_FLOPS = {"35b8a367b0d3ebaa": {"fp64": 54.9}}
 
 
 def kernel_name(shape, fp64):

@@ -15,7 +15,7 @@
 //
 // Decomposition. Bodies form blocks of B = NW * 64 * kSymIPL (a workgroup holds one
 // block in registers, kSymIPL per lane), each cut into P parts of H = B / P bodies
-// (P from 2 to 12, more for smaller systems so that there are enough units). A unit
+// (P from 1 to 12, more for smaller systems so that there are enough units). A unit
 // is (row block I, part of a block): the first P units of row I are the parts of
 // block I itself (taken one-sided: every i of the block against every j of the part,
 // self pair masked), then the parts of the blocks J > I (taken symmetrically). Units
@@ -348,8 +348,22 @@ __global__ __launch_bounds__(64 * NW, 2) void k_eval_sym(Arrays A, int n, int nb
     }
 }
 
+// A running sum with Neumaier's compensation: s + c carries the sum of the added
+// values with the rounding of each addition kept in c.
+struct CompSum {
+    double s = 0.0, c = 0.0;
+    __device__ __forceinline__ void add(double x)
+    {
+        const double t = s + x;
+        c += (fabs(s) >= fabs(x)) ? ((s - t) + x) : ((x - t) + s);
+        s = t;
+    }
+};
+
 // Per (index-list entry, component): the row slots of the body's block and its
-// column slots, each in four interleaved running sums, combined in a fixed pattern.
+// column slots, each in four interleaved compensated running sums (the pass is bound
+// by its loads, so the compensation is free and the result carries no rounding of
+// this pass beyond the last addition), combined in a fixed pattern.
 template <int B>
 __global__ __launch_bounds__(256) void k_sym_reduce(Arrays A, int n, const int32_t *__restrict__ idx,
                                                     int n_act, int P, int64_t split0, int fine,
@@ -376,30 +390,42 @@ __global__ __launch_bounds__(256) void k_sym_reduce(Arrays A, int n, const int32
     const double *row = rowbuf + ((size_t)v0 * 10 + c) * B + r;
     const int nrow = (int)(item_of(row_start(K + 1, nb, P), split0, fine) - v0);
     const size_t rs = (size_t)10 * B;
-    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    CompSum s0, s1, s2, s3;
     int k = 0;
     for (; k + 3 < nrow; k += 4) {
-        s0 += row[k * rs];
-        s1 += row[(k + 1) * rs];
-        s2 += row[(k + 2) * rs];
-        s3 += row[(k + 3) * rs];
+        const double x0 = row[k * rs], x1 = row[(k + 1) * rs], x2 = row[(k + 2) * rs],
+                     x3 = row[(k + 3) * rs];
+        s0.add(x0);
+        s1.add(x1);
+        s2.add(x2);
+        s3.add(x3);
     }
     for (; k < nrow; ++k)
-        s0 += row[k * rs];
+        s0.add(row[k * rs]);
     const double *col = colbuf + (size_t)K * (K - 1) / 2 * P * 10 * H + (size_t)part * 10 * H +
                         (size_t)c * H + (r - part * H);
     const size_t cs = (size_t)P * 10 * H;
-    double t0 = 0.0, t1 = 0.0, t2 = 0.0, t3 = 0.0;
+    CompSum t0, t1, t2, t3;
     int I = 0;
     for (; I + 3 < K; I += 4) {
-        t0 += col[I * cs];
-        t1 += col[(I + 1) * cs];
-        t2 += col[(I + 2) * cs];
-        t3 += col[(I + 3) * cs];
+        const double x0 = col[I * cs], x1 = col[(I + 1) * cs], x2 = col[(I + 2) * cs],
+                     x3 = col[(I + 3) * cs];
+        t0.add(x0);
+        t1.add(x1);
+        t2.add(x2);
+        t3.add(x3);
     }
     for (; I < K; ++I)
-        t0 += col[I * cs];
-    const double s = ((s0 + s1) + (s2 + s3)) + ((t0 + t1) + (t2 + t3));
+        t0.add(col[I * cs]);
+    CompSum tot;
+    const CompSum *parts[8] = {&s0, &s1, &s2, &s3, &t0, &t1, &t2, &t3};
+    double comp = 0.0;
+#pragma unroll
+    for (int p = 0; p < 8; ++p) {
+        tot.add(parts[p]->s);
+        comp += parts[p]->c;
+    }
+    const double s = tot.s + (tot.c + comp);
     out[(size_t)c * n_act + q] = s;
     if (out2)
         out2[(size_t)c * n_act + q] = s;
@@ -409,7 +435,7 @@ __global__ __launch_bounds__(256) void k_sym_reduce(Arrays A, int n, const int32
 
 // Geometry of the symmetric evaluation of n bodies by G workgroups.
 // Parts per block: the fewest (longest units, fewest row partials) that still give
-// every workgroup about eight units to claim. The last units, as many as there are
+// every workgroup about seven units to claim. The last units, as many as there are
 // workgroups and at most a quarter of all, are cut into pieces of 128 records (64
 // when H is not a multiple of 128), so that the end of the launch, where the last
 // claims finish, is short against the whole.
@@ -419,10 +445,10 @@ SymPlan plan_sym(int64_t n, int G)
     P.B = kSymWaves * 64 * kSymIPL;
     P.nb = (int)((n + P.B - 1) / P.B);
     const int64_t pairs = (int64_t)P.nb * (P.nb + 1) / 2;  // blocks (I, J >= I)
-    static const int kParts[] = {2, 3, 4, 6, 12};          // B / P a multiple of 64
+    static const int kParts[] = {1, 2, 3, 4, 6, 12};       // B / P a multiple of 64
     P.parts = 12;
     for (int p : kParts)
-        if (p * pairs >= 8 * (int64_t)G) {
+        if (p * pairs >= 7 * (int64_t)G) {
             P.parts = p;
             break;
         }
