@@ -310,7 +310,7 @@ nb_status nb_timesteps(nb_ctx *ctx, const int32_t *d_idx, int64_t n_act, int ini
 nb_status nb_step(nb_ctx *ctx, int64_t tick_limit, int64_t *h_n_act, int64_t *h_tick_next);
 
 /* Passage: the energy diagnostic of a direct N-body code (the paper reports no energy
- * error; this is the softened total energy used to judge the integration).
+ * error; this is the softened total energy used to check the integration).
  * Total energy at tick: every body is predicted to tick (this overwrites the
  * predicted state), then E_kin = sum m v^2 / 2 and
  * E_pot = -1/2 sum_i sum_{j != i} m_i m_j / sqrt(r^2 + eps^2). Waits. */
