@@ -267,7 +267,8 @@ nb_status nb_set_evaluation(nb_ctx *ctx, const int32_t *d_idx, int64_t n_act,
  * unsupported combination. h_shape_out (may be NULL; 7 int32) receives the shape the
  * next call with n_act bodies will use: {ipl (for the small-set and group kernels:
  * -P or -G), waves, tile, jchunk, splits, iblocks (groups), fused (1: the splits are
- * added inside the evaluation launch)}. */
+ * added inside the evaluation launch)}; for the pairwise-symmetric kernel {0, waves,
+ * 64, records per unit, claimed units and pieces, workgroups, 0}. */
 nb_status nb_eval_config(nb_ctx *ctx, const int32_t *h_cfg, int64_t n_act,
                          int32_t *h_shape_out);
 
